@@ -1,0 +1,221 @@
+"""Seeded synthetic inputs: jittered periodic triangle meshes and initial states.
+
+This module holds no arithmetic of the reconstruction or flux method. It only
+builds meshes (vertex coordinates and triangle lists) and cell-average initial
+states, which both the CPU oracle and the HIP path consume unchanged.
+
+Mesh recipe (periodic unit square, N x N squares, two triangles each):
+  * h = 1/N; vertex (i, j) has id j*N + i and sits at (i*h + jx, j*h + jy),
+    where jx and jy are drawn U[-0.2h, 0.2h]: first all jx, then all jy, each
+    as an (N, N) array indexed [j, i] from ``np.random.default_rng(seed)``.
+  * square (i, j) has corners v00=(i,j), v10=(i+1,j), v11=(i+1,j+1),
+    v01=(i,j+1) (indices mod N) and is split along v00-v11 into cells
+    2(jN+i) = (v00, v10, v11) and 2(jN+i)+1 = (v00, v11, v01).
+  * the initial-state parameters are drawn from the same generator afterwards.
+
+Initial states (conservative variables rho, rho*u, rho*v, E; gamma = 1.4):
+  * ``smooth_wave``: rho = 1 + 0.2 sin(2 pi (x + y)), u = v = p = 1, as exact
+    cell averages up to a 64-point product Gauss rule per triangle.  This is an
+    exact Euler solution translating with velocity (1, 1).
+  * ``random_lines``: two random lines split the torus into four regions with
+    piecewise-constant states rho ~ U[0.1, 1.5], u, v ~ U[-1, 1],
+    p ~ U[0.03, 1.5], sampled at cell centroids wrapped into [0, 1)^2.
+  * ``wave_plus_jump``: the smooth wave with p multiplied by a ratio
+    ~ U[2, 10] on the positive side of one random line.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+@dataclass
+class MeshData:
+    n: int
+    xy: np.ndarray          # [n_vert, 2] float64
+    tri: np.ndarray         # [n_cell, 3] int32 (counter-clockwise)
+    period: tuple = (1.0, 1.0)
+    seed: int = 0
+    rng: np.random.Generator = field(default=None, repr=False)
+
+    @property
+    def n_cell(self) -> int:
+        return int(self.tri.shape[0])
+
+    @property
+    def n_vert(self) -> int:
+        return int(self.xy.shape[0])
+
+
+def jittered_periodic_mesh(n: int, seed: int, jitter: float = 0.2) -> MeshData:
+    """N x N x 2 jittered periodic triangulation of the unit torus."""
+    if n < 2:
+        raise ValueError("n must be >= 2")
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    jx = rng.uniform(-jitter * h, jitter * h, size=(n, n))
+    jy = rng.uniform(-jitter * h, jitter * h, size=(n, n))
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    xy = np.stack([ii * h + jx, jj * h + jy], axis=-1).reshape(-1, 2)
+    ip = (ii + 1) % n
+    jp = (jj + 1) % n
+    v00 = jj * n + ii
+    v10 = jj * n + ip
+    v11 = jp * n + ip
+    v01 = jp * n + ii
+    tri = np.empty((n * n, 2, 3), dtype=np.int32)
+    tri[:, 0, 0] = v00.ravel()
+    tri[:, 0, 1] = v10.ravel()
+    tri[:, 0, 2] = v11.ravel()
+    tri[:, 1, 0] = v00.ravel()
+    tri[:, 1, 1] = v11.ravel()
+    tri[:, 1, 2] = v01.ravel()
+    return MeshData(n=n, xy=np.ascontiguousarray(xy, dtype=np.float64),
+                    tri=np.ascontiguousarray(tri.reshape(-1, 3)), seed=seed, rng=rng)
+
+
+def unwrapped_vertices(mesh: MeshData) -> np.ndarray:
+    """[n_cell, 3, 2] vertex coordinates with v1, v2 moved to the periodic
+    image nearest to v0."""
+    p = np.asarray(mesh.period, dtype=np.float64)
+    v = mesh.xy[mesh.tri]                      # [nc, 3, 2]
+    d = v - v[:, :1, :]
+    v = v - np.round(d / p) * p
+    return v
+
+
+def centroids(mesh: MeshData, wrap: bool = True) -> np.ndarray:
+    c = unwrapped_vertices(mesh).mean(axis=1)
+    if wrap:
+        p = np.asarray(mesh.period)
+        c = c - np.floor(c / p) * p
+    return c
+
+
+def _gauss01(n: int):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def triangle_average(mesh: MeshData, f, npts: int = 8) -> np.ndarray:
+    """Cell averages of f(x, y) (vectorised) by a collapsed product Gauss rule."""
+    v = unwrapped_vertices(mesh)
+    t, w = _gauss01(npts)
+    uu, ww = np.meshgrid(t, t, indexing="ij")
+    wgt = (w[:, None] * w[None, :]) * uu * 2.0        # sums to 1 over the triangle
+    q0, q1, q2 = v[:, 0], v[:, 1], v[:, 2]
+    x = (q0[:, None, None, :] + uu[None, :, :, None] * (q1 - q0)[:, None, None, :]
+         + (uu * ww)[None, :, :, None] * (q2 - q1)[:, None, None, :])
+    vals = f(x[..., 0], x[..., 1])
+    return (vals * wgt[None]).sum(axis=(1, 2))
+
+
+def conservative(rho, u, v, p, gamma: float = GAMMA) -> np.ndarray:
+    rho = np.asarray(rho, dtype=np.float64)
+    u = np.broadcast_to(np.asarray(u, dtype=np.float64), rho.shape)
+    v = np.broadcast_to(np.asarray(v, dtype=np.float64), rho.shape)
+    p = np.broadcast_to(np.asarray(p, dtype=np.float64), rho.shape)
+    e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, e], axis=-1))
+
+
+def smooth_wave_density(x, y, t: float = 0.0):
+    return 1.0 + 0.2 * np.sin(2.0 * math.pi * (x + y - 2.0 * t))
+
+
+def smooth_wave(mesh: MeshData, t: float = 0.0, npts: int = 8) -> np.ndarray:
+    """Exact cell averages of the translating density wave at time t."""
+    rho = triangle_average(mesh, lambda x, y: smooth_wave_density(x, y, t), npts)
+    return conservative(rho, 1.0, 1.0, 1.0)
+
+
+def _random_line(rng):
+    c = rng.uniform(0.0, 1.0, size=2)
+    th = rng.uniform(0.0, math.pi)
+    return c, np.array([math.cos(th), math.sin(th)])
+
+
+def random_lines(mesh: MeshData, rng: np.random.Generator | None = None) -> np.ndarray:
+    rng = mesh.rng if rng is None else rng
+    c1, n1 = _random_line(rng)
+    c2, n2 = _random_line(rng)
+    states = []
+    for _ in range(4):
+        rho = rng.uniform(0.1, 1.5)
+        u = rng.uniform(-1.0, 1.0)
+        v = rng.uniform(-1.0, 1.0)
+        p = rng.uniform(0.03, 1.5)
+        states.append((rho, u, v, p))
+    states = np.array(states)
+    x = centroids(mesh, wrap=True)
+    reg = 2 * (((x - c1) @ n1) >= 0.0).astype(np.int64) + (((x - c2) @ n2) >= 0.0).astype(np.int64)
+    s = states[reg]
+    return conservative(s[:, 0], s[:, 1], s[:, 2], s[:, 3])
+
+
+def wave_plus_jump(mesh: MeshData, rng: np.random.Generator | None = None) -> np.ndarray:
+    rng = mesh.rng if rng is None else rng
+    c, nrm = _random_line(rng)
+    ratio = rng.uniform(2.0, 10.0)
+    rho = triangle_average(mesh, lambda x, y: smooth_wave_density(x, y), 8)
+    x = centroids(mesh, wrap=True)
+    p = np.where(((x - c) @ nrm) >= 0.0, ratio, 1.0)
+    return conservative(rho, 1.0, 1.0, p)
+
+
+def disc_mask(mesh: MeshData, center, radius: float) -> np.ndarray:
+    """Cells whose centroid lies within `radius` of `center` (periodic distance)."""
+    x = centroids(mesh, wrap=True)
+    d = x - np.asarray(center)
+    p = np.asarray(mesh.period)
+    d = d - np.round(d / p) * p
+    return (d * d).sum(axis=1) <= radius * radius
+
+
+# ---------------------------------------------------------------------------
+# The five workloads: (order, mesh size, seed, initial state, steps)
+# ---------------------------------------------------------------------------
+WORKLOADS = {
+    1: dict(name="teno3_wave_N32", order=3, n=32, seed=1, ic="smooth_wave", steps=10),
+    2: dict(name="teno5_lines_N512", order=5, n=512, seed=2, ic="random_lines", steps=100),
+    3: dict(name="teno6_wavejump_N1024", order=6, n=1024, seed=3, ic="wave_plus_jump", steps=50),
+    4: dict(name="teno4_adjoint_N256", order=4, n=256, seed=4, ic="random_lines", steps=200),
+}
+
+
+def make_state(mesh: MeshData, ic: str) -> np.ndarray:
+    if ic == "smooth_wave":
+        return smooth_wave(mesh)
+    if ic == "random_lines":
+        return random_lines(mesh)
+    if ic == "wave_plus_jump":
+        return wave_plus_jump(mesh)
+    raise ValueError(ic)
+
+
+def make_workload(key: int, n: int | None = None):
+    """Mesh + initial state of a named workload (optionally at another size)."""
+    w = dict(WORKLOADS[key])
+    if n is not None:
+        w["n"] = n
+    mesh = jittered_periodic_mesh(w["n"], w["seed"])
+    u0 = make_state(mesh, w["ic"])
+    return w, mesh, u0
+
+
+def adjoint_loss_disc(mesh: MeshData):
+    """Disc of radius 0.1 with a seeded centre (drawn after the initial state)."""
+    center = mesh.rng.uniform(0.0, 1.0, size=2)
+    return center, 0.1
+
+
+def batch_specs(n_mesh: int = 64, seed: int = 5, nmin: int = 32, nmax: int = 316):
+    """(N, order, seed) of each mesh of the batched workload."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(nmin, nmax + 1, size=n_mesh)
+    ps = rng.integers(3, 7, size=n_mesh)
+    return [(int(ns[m]), int(ps[m]), 5000 + m) for m in range(n_mesh)]
