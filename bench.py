@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the TENO residual hot path on one MI355X.
+
+One step = one SSP-RK3 step of the whole hot path on the device: the
+constant-CFL time step, then three stages of (reconstruction with TENO
+selection -> HLL face fluxes -> residual gather -> stage update).  The
+headline workload is 5th-order TENO on a jittered periodic 512 x 512 x 2
+mesh (524,288 triangles) with the seeded four-region random-line state.
+
+Prints ONE JSON line (see the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "tables.h"):
+        with open(os.path.join(ROOT, "paper_2105_02127_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_reconstruct(order: int, nq: int) -> int:
+    """Bytes one cell must move through the reconstruction kernel per stage:
+    its least-squares operators (3 small 5x11 + large nu x nl, FP64), its
+    stencil indices (int32), its own state (read once), its face-point
+    states (written once) and its selection flags."""
+    r = order - 1
+    nu = (r + 1) * (r + 2) // 2 - 1
+    nl = (r + 1) * (r + 2) - 1
+    ops = 8 * (3 * 5 * 11 + nu * nl)
+    idx = 4 * (33 + nl)
+    return ops + idx + 32 + 3 * nq * 32 + 2
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per reconstruction launch from the committed rocprofv3 PMC
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_reconstruct_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(mesh, U, order, fallback, steps=1):
+    """The CPU oracle (as it stands) on the same mesh and state: one full
+    SSP-RK3 step over every cell, set-up excluded, all host threads."""
+    import oracle
+    threads = oracle.get_threads()
+    om = oracle.OracleMesh(mesh.xy, mesh.tri)
+    t0 = time.perf_counter()
+    om.setup(oracle.params(order=order, fallback=fallback))
+    t_setup = time.perf_counter() - t0
+    dt = om.dt(U, 0.4)
+    t0 = time.perf_counter()
+    Uc = U
+    for _ in range(steps):
+        Uc = om.rk_step(Uc, dt)["U"]
+    t = time.perf_counter() - t0
+    return {"value": mesh.n_cell * 3 * steps / t, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} full SSP-RK3 step(s) ({3 * steps} stages) over all {mesh.n_cell} cells "
+                      f"of the same mesh and state; oracle set-up ({t_setup:.1f} s) excluded",
+            "seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=2, help="2 = TENO5 512^2 lines, 3 = TENO6 1024^2")
+    ap.add_argument("--n", type=int, default=None, help="override mesh size N (N x N x 2 cells)")
+    ap.add_argument("--fallback", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the residual would shard by domain decomposition with one ghost exchange "
+              "per stage; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_02127_amd import inputs, teno
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    w, mesh, U0 = inputs.make_workload(args.workload, n=args.n)
+    order = w["order"]
+    t0 = time.perf_counter()
+    lm = teno.Mesh(mesh.xy, mesh.tri).setup(order=order, fallback=args.fallback)
+    t_setup = time.perf_counter() - t0
+    sv = teno.Solver(lm)
+    info = lm.info()
+    Ud = torch.as_tensor(U0[lm.perm], device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sv.max_dt(Ud, 0.4, dt)
+        sv.rk_step(Ud, dt)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sv.diagnostics(reset=True)
+    sv.profile_read(reset=True)
+    sv.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sv.profile_enable(False)
+    prof = sv.profile_read(reset=True)
+    diag = sv.diagnostics(reset=True)
+
+    n_cell = mesh.n_cell
+    stages = 3 * args.steps
+    value = n_cell * stages / elapsed
+    nq = info.n_quad
+    k1_ms = prof.ms["reconstruct"] / max(1, prof.launches["reconstruct"])
+    k2_ms = prof.ms["flux_update"] / max(1, prof.launches["flux_update"])
+    bytes_k1 = algorithmic_bytes_reconstruct(order, nq) * n_cell
+    achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(w["name"])
+    out = {
+        "metric": "cell-updates/s per RK stage (5th-order, Euler)" if order == 5 else
+                  f"cell-updates/s per RK stage ({order}th-order, Euler)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n_cell": n_cell, "order": order, "n_quad": nq,
+                   "ic": w["ic"], "seed": w["seed"], "cfl": 0.4,
+                   "positivity_fallback": bool(args.fallback),
+                   "stage": "reconstruct + HLL flux + gather + RK update; dt once per step"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_reconstruct",
+                     "algorithmic_bytes_per_launch": bytes_k1,
+                     "avg_launch_ms": k1_ms},
+        "kernels_ms_per_launch": {"reconstruct": k1_ms, "flux_update": k2_ms,
+                                  "dt": prof.ms["dt"] / max(1, prof.launches["dt"])},
+        "diagnostics": diag,
+        "setup_s": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

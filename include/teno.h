@@ -1,0 +1,187 @@
+/*
+ * teno.h -- C ABI of libteno: the per-cell, per-Runge-Kutta-stage residual of
+ * the unstructured-mesh finite-volume TENO scheme (Ji, Liang & Fu, "A class of
+ * new high-order finite-volume TENO schemes for hyperbolic conservation laws
+ * with unstructured meshes") for the 2D Euler equations on periodic triangle
+ * meshes, in FP64, on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every call
+ *  - Return value: TENO_OK (0) or a negative teno_status; teno_last_error()
+ *    returns a message for the calling thread.  No C++ exception crosses the
+ *    ABI.  Argument and shape errors are reported synchronously.
+ *  - State arrays (U, R, lambda, U_bar) are caller-owned DEVICE pointers to
+ *    double[n_cell][4] = (rho, rho*u, rho*v, E), contiguous, in the library's
+ *    INTERNAL cell order (see teno_mesh_permutation).  Flags are caller-owned
+ *    device uint16_t[n_cell].  dt is a caller-owned device double.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
+ *    NULL = legacy default stream) and returns without synchronising, except
+ *    where a call says otherwise.  Per-step calls never allocate.
+ *  - Mesh and set-up calls are host-only (no GPU needed).
+ */
+#ifndef TENO_H
+#define TENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum teno_status {
+  TENO_OK = 0,
+  TENO_EARG = -1,      /* bad argument, size or state of the object            */
+  TENO_EMESH = -2,     /* degenerate triangle, open or non-manifold edge       */
+  TENO_ESTENCIL = -3,  /* mesh too small for the requested stencils            */
+  TENO_ERANK = -4,     /* rank-deficient least-squares matrix                  */
+  TENO_EHIP = -5,      /* HIP runtime error (message names the call)           */
+  TENO_ENOMEM = -6     /* host or device allocation failed                     */
+} teno_status;
+
+typedef struct teno_mesh teno_mesh;
+typedef struct teno_solver teno_solver;
+
+/* Scheme parameters.  Defaults (teno_default_params) are the paper's fixed
+ * built-in values: C_T = 1e-6 in both selection steps and eps = 1e-12 with
+ * exponent 6 in the scale separation (Sec. 3.2-3.3), gamma = 1.4. */
+typedef struct teno_params {
+  int32_t order;     /* 3..6: large-stencil degree order-1, Sec. 2.2 eq. 03   */
+  int32_t n_quad;    /* Gauss points per face, 0 = ceil(order/2)              */
+  int32_t variant;   /* 0 = TENO (Sec. 3), 1 = LINEAR (large stencil only)    */
+  int32_t power;     /* scale-separation exponent (paper: 6)                  */
+  double ct;         /* cutoff C_T in [0, 1/3] (paper: 1e-6)                  */
+  double eps;        /* epsilon of the scale separation (paper: 1e-12)        */
+  double gamma;      /* ratio of specific heats                               */
+  double tie_rel;    /* near-tie band: |chi/C_T - 1| <= tie_rel is counted    */
+  int32_t fallback;  /* 1: a cell with a non-physical face state uses its    */
+                     /* cell average on every face and flags 0 (not in the   */
+                     /* paper; default 0)                                     */
+  int32_t reorder;   /* 1 = Morton order of cells (default), 0 = user order   */
+  int32_t n_threads; /* host threads for set-up, 0 = hardware concurrency     */
+  int32_t reserved;
+} teno_params;
+
+typedef struct teno_info {
+  int32_t n_cell, n_face, order, n_quad;
+  int32_t n_coef_large, rows_large;  /* unknowns / rows of the large stencil */
+  int32_t n_coef_small, rows_small;  /* 5 / 11 for the third-order stencils  */
+  int64_t matrix_doubles_per_cell;   /* streamed pseudo-inverse entries      */
+  int64_t device_bytes;              /* library-owned device memory          */
+  double min_rcond;                  /* min over stencils of min|R_jj|/max|R_jj| */
+} teno_info;
+
+/* Device-side diagnostics, accumulated until reset. */
+typedef struct teno_diag {
+  int64_t nonphysical;    /* cells with rho<=0, p<=0 or NaN at the average or */
+                          /* a face point, per reconstruction                 */
+  int64_t first_bad_cell; /* lowest USER id among them, -1 if none            */
+  int64_t near_ties;      /* chi within tie_rel of C_T                        */
+  int64_t fallbacks;      /* cells reconstructed at first order               */
+} teno_diag;
+
+const char* teno_last_error(void);
+void teno_default_params(teno_params* p);
+
+/* ---- mesh and set-up (host only) --------------------------------------- */
+
+/* Geometry and faces, Sec. 2.1.  xy: host double[n_vert][2]; tri: host
+ * int32[n_cell][3] (orientation fixed to counter-clockwise internally by
+ * swapping the last two vertices); period: host double[2] of the periodic box,
+ * or NULL.  Every edge must be shared by exactly two cells (closed periodic
+ * mesh), else TENO_EMESH.  Copies its inputs; *out is owned by the caller. */
+int teno_mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
+                     const double* period, teno_mesh** out);
+
+/* Stencils (Sec. 3.1: one central stencil of 2N_k cells incl. the target and
+ * three directional third-order stencils of 12 cells), reference-space
+ * least-squares matrices and their Householder pseudo-inverses
+ * (Sec. 2.2 eqs. 02-10), cell reordering and device packing.
+ * Errors: TENO_ESTENCIL, TENO_ERANK, TENO_EARG. */
+int teno_mesh_setup(teno_mesh* m, const teno_params* p);
+
+int teno_mesh_info(const teno_mesh* m, teno_info* out);
+
+/* perm[internal] = user cell id (host int32[n_cell]). */
+int teno_mesh_permutation(const teno_mesh* m, int32_t* perm);
+
+/* Members of stencil k (0..2 directional across local edge k, 3 = central)
+ * of USER cell `cell`, as user ids nearest first, target excluded. Returns the
+ * row count. */
+int teno_mesh_stencil(const teno_mesh* m, int32_t cell, int32_t k, int32_t* members);
+
+/* Least-squares operator of that stencil: coef = M (U_s - U_0) with
+ * M = pinv(A) diag(|V'_s|), host double[n_coef][rows] row-major.
+ * Returns the row count. */
+int teno_mesh_lsq_operator(const teno_mesh* m, int32_t cell, int32_t k, double* M);
+
+void teno_mesh_destroy(teno_mesh* m);
+
+/* ---- solver: device data and per-stage work ---------------------------- */
+
+/* Uploads mesh, stencil and matrix data to `device` and allocates all
+ * workspaces; the only allocating call.  Requires teno_mesh_setup. */
+int teno_solver_create(const teno_mesh* m, int32_t device, teno_solver** out);
+void teno_solver_destroy(teno_solver* s);
+
+/* Semi-discrete residual R(U) = dU/dt, Sec. 2.1 semi-discrete equation:
+ * reconstruction with TENO selection (Sec. 2.2-3.3), rotated HLL flux at the
+ * face Gauss points (Sec. 4), face-flux gather per cell.  flags (nullable):
+ * output, bit 4v+3 = large stencil kept for variable v, bits 4v..4v+2 = small
+ * stencil kept in the second selection step. */
+int teno_residual(teno_solver* s, const double* U, double* R, uint16_t* flags, void* stream);
+
+/* Same residual with the selection frozen to `flags` (input). */
+int teno_residual_frozen(teno_solver* s, const double* U, double* R, const uint16_t* flags,
+                         void* stream);
+
+/* Reconstruction only: face-point states of every cell, device
+ * double[3*n_quad][n_cell][4] (point e*n_quad+kappa of local edge e, Gauss
+ * point kappa along the edge from its first vertex), and flags (nullable). */
+int teno_reconstruct(teno_solver* s, const double* U, double* face_states, uint16_t* flags,
+                     void* stream);
+
+/* dt = cfl * min_i |V_i| / sum_j |A_ij| (|u_i . n_ij| + c_i) from the cell
+ * averages (constant-CFL step of Sec. 5), written to device *dt_dev. */
+int teno_max_dt(teno_solver* s, const double* U, double cfl, double* dt_dev, void* stream);
+
+/* One stage of SSP-RK3 (Sec. 2.1 time discretisation), k = 0, 1, 2:
+ *   k=0: Uk1 = Un + dt R(Un)                      (Uk must equal Un)
+ *   k=1: Uk1 = 3/4 Un + 1/4 Uk + 1/4 dt R(Uk)
+ *   k=2: Uk1 = 1/3 Un + 2/3 Uk + 2/3 dt R(Uk)
+ * Uk1 may alias Un (each cell reads only its own Un).  flags nullable (out),
+ * or input when frozen != 0. */
+int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk, double* Uk1,
+                  const double* dt_dev, uint16_t* flags, int32_t frozen, void* stream);
+
+/* One full SSP-RK3 step in place on U using library-owned stage buffers.
+ * flags3: nullable device uint16_t[3][n_cell] (out, or in when frozen != 0).
+ * stages: nullable device double[3][n_cell][4], receives the stage inputs
+ * U^n, U^(1), U^(2) (what the adjoint needs). */
+int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flags3,
+                 int32_t frozen, double* stages, void* stream);
+
+/* Adjoint of the residual with the selection frozen to `flags`:
+ * U_bar = (dR/dU)^T lam.  The reconstruction is linear in U for fixed
+ * selection, so this is exact wherever the HLL flux is differentiable. */
+int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
+                      double* U_bar, void* stream);
+
+/* Adjoint of one SSP-RK3 step (frozen dt and selection): given the stage
+ * inputs (teno_rk_step's `stages`), their flags3 and lam_out = adjoint of
+ * U^{n+1}, writes lam_in = adjoint of U^n.  lam_in may alias lam_out. */
+int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags3,
+                     const double* dt_dev, const double* lam_out, double* lam_in, void* stream);
+
+/* Reads (and optionally resets) the device diagnostics; synchronises the
+ * stream. */
+int teno_diagnostics(teno_solver* s, teno_diag* out, int32_t reset, void* stream);
+
+/* Kernel timing with HIP events around every launch (off by default).
+ * teno_profile_read returns, per kernel kind (0 reconstruct, 1 flux+update,
+ * 2 dt, 3 adjoint), the summed milliseconds and launch counts; synchronises. */
+int teno_profile_enable(teno_solver* s, int32_t on);
+int teno_profile_read(teno_solver* s, double* ms, int64_t* launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TENO_H */

@@ -1,0 +1,90 @@
+// Library-internal data shared by the host set-up and the device launches.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/teno.h"
+
+namespace teno {
+
+// Cells per wavefront tile: one 64-lane wavefront handles 16 cells x 4
+// conservative variables in the reconstruction kernel.
+constexpr int kTile = 16;
+
+// Sizes of one order (Sec. 2.2 eq. 03 with N_k counting the constant term;
+// N_s = 2 N_k cells including the target, so 2 N_k - 1 least-squares rows).
+struct Dims {
+  int order = 0, r = 0;
+  int nu = 0;      // unknowns of the large stencil, N_k - 1
+  int nl = 0;      // rows of the large stencil
+  int nq = 0;      // Gauss points per face
+  int rows = 0;    // all stencil rows: 3 * 11 small + nl
+  int rows4 = 0;   // rows rounded up to a multiple of 4 (int4 loads)
+  int J = 0;       // operator entries per cell: 3 * 5 * 11 + nu * nl
+  int J2 = 0;      // J rounded up to pairs (double2 loads)
+};
+
+Dims dims_for(int order, int nq_req);
+
+constexpr int kSmallRows = 11;
+constexpr int kSmallCoef = 5;
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+struct Mesh {
+  // ---- geometry, user order ----
+  int nv = 0, nc = 0, nf = 0;
+  bool periodic = false;
+  double P[2] = {0.0, 0.0};
+  std::vector<int32_t> tri;           // [nc][3] counter-clockwise
+  std::vector<double> X;              // [nc][3][2] vertices unwrapped about v0
+  std::vector<double> area, cen;      // [nc], [nc][2]
+  std::vector<int32_t> fL, fR, fLe, fRe;  // face -> L/R cell (user id), local edges
+  std::vector<double> fnx, fny, flen;     // unit normal out of L, edge length
+  std::vector<int32_t> cface;         // [nc][3] face of each local edge
+
+  // ---- set-up ----
+  bool ready = false;
+  teno_params prm{};
+  Dims d;
+  std::vector<int32_t> perm, inv;     // perm[internal] = user, inv[user] = internal
+  double min_rcond = 1.0;
+
+  // ---- packed device images, internal order, tile-major ----
+  int n_pad = 0, n_tiles = 0;
+  std::vector<int32_t> idx;     // [n_tiles][rows4][16][4] stencil members (internal)
+  std::vector<double> M;        // [n_tiles][J2][16][2] operator entries
+  std::vector<int32_t> nbinfo;  // [n_pad][4]: 3 neighbours + packed edge/side bits
+  std::vector<double> geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area
+  std::vector<int32_t> user_of; // [n_pad] user id (diagnostics)
+  // reverse stencil (adjoint gather): cells i whose row r names cell j
+  std::vector<int32_t> rev_ptr; // [n_cell + 1]
+  std::vector<int32_t> rev_ent; // i * rows4*4 + r, internal ids
+};
+
+// Entry j of the operator stream of one cell:
+//   small stencil k (0..2), row s, coefficient l: j = k*55 + s*5 + l
+//   large stencil row s, coefficient l:           j = 165 + s*nu + l
+// Stencil row order: rows 0..32 small stencils (11 each), then nl large rows.
+inline int64_t packed_M_index(const Mesh& m, int internal, int j) {
+  int t = internal / kTile, c = internal % kTile;
+  return (((int64_t)t * m.d.J2 + (j >> 1)) * kTile + c) * 2 + (j & 1);
+}
+
+inline int64_t packed_idx_index(const Mesh& m, int internal, int row) {
+  int t = internal / kTile, c = internal % kTile;
+  return (((int64_t)t * m.d.rows4 + (row >> 2)) * kTile + c) * 4 + (row & 3);
+}
+
+int mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
+                const double* period, Mesh& m);
+int mesh_setup(Mesh& m, const teno_params& p);
+
+}  // namespace teno
+
+struct teno_mesh {
+  teno::Mesh m;
+};

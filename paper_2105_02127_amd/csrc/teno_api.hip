@@ -1,0 +1,641 @@
+// C ABI of libteno (include/teno.h): argument checks, device buffers and
+// kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.hpp"
+
+namespace teno {
+const char* last_error();
+}
+
+using namespace teno;
+
+namespace {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(IC<P>, IC<NQ>) for the supported (order, face points) pairs.
+template <class F>
+bool dispatch(int P, int NQ, F&& f) {
+  switch (P * 10 + NQ) {
+    case 32: f(IC<3>{}, IC<2>{}); return true;
+    case 33: f(IC<3>{}, IC<3>{}); return true;
+    case 42: f(IC<4>{}, IC<2>{}); return true;
+    case 43: f(IC<4>{}, IC<3>{}); return true;
+    case 52: f(IC<5>{}, IC<2>{}); return true;
+    case 53: f(IC<5>{}, IC<3>{}); return true;
+    case 62: f(IC<6>{}, IC<2>{}); return true;
+    case 63: f(IC<6>{}, IC<3>{}); return true;
+    default: return false;
+  }
+}
+
+struct DeviceScope {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(TENO_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct teno_solver {
+  int device = 0;
+  Dims d;
+  teno_params prm{};
+  int n_cell = 0, n_pad = 0, n_tiles = 0;
+  int4* idx = nullptr;
+  double2* M = nullptr;
+  int4* nbinfo = nullptr;
+  double* geo = nullptr;
+  int32_t* user_of = nullptr;
+  int32_t* rev_ptr = nullptr;
+  int32_t* rev_ent = nullptr;
+  double* fp = nullptr;
+  double* fpbar = nullptr;
+  double* dbar = nullptr;
+  double* own = nullptr;
+  double* W1 = nullptr;
+  double* W2 = nullptr;
+  double* T0 = nullptr;
+  double* T1 = nullptr;
+  double* T2 = nullptr;
+  double* dtpart = nullptr;
+  int n_dtblk = 0;
+  DevDiag* diag = nullptr;
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  // profiling
+  bool prof = false;
+  struct Ev {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> evs;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_n[4] = {0, 0, 0, 0};
+
+  template <class T>
+  int alloc(T*& p, size_t count) {
+    void* q = nullptr;
+    size_t nb = std::max<size_t>(count * sizeof(T), 256);
+    hipError_t e = hipMalloc(&q, nb);
+    if (e != hipSuccess) return fail(TENO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    allocs.push_back(q);
+    bytes += (int64_t)nb;
+    p = (T*)q;
+    return TENO_OK;
+  }
+  ~teno_solver() {
+    for (auto& e : evs) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto& e : pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    for (void* q : allocs) (void)hipFree(q);
+  }
+};
+
+namespace {
+
+// Records kernel timing around `launch` when profiling is on.
+template <class F>
+int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (s->prof) {
+    if (!s->pool.empty()) {
+      ev = s->pool.back();
+      s->pool.pop_back();
+    } else {
+      if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess)
+        return fail(TENO_EHIP, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(ev.first, st);
+  }
+  launch();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  if (s->prof) {
+    (void)hipEventRecord(ev.second, st);
+    s->evs.push_back({kind, ev.first, ev.second});
+  }
+  return TENO_OK;
+}
+
+int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool frozen,
+                       hipStream_t st) {
+  ReconArgs a;
+  a.U = U;
+  a.idx = s->idx;
+  a.M = s->M;
+  a.fp = s->fp;
+  a.flags = flags;
+  a.user_of = s->user_of;
+  a.diag = s->diag;
+  a.n_cell = s->n_cell;
+  a.n_tiles = s->n_tiles;
+  a.n_pad = s->n_pad;
+  a.frozen = frozen ? 1 : 0;
+  a.variant = s->prm.variant;
+  a.fallback = s->prm.fallback;
+  a.power = s->prm.power;
+  a.ct = s->prm.ct;
+  a.eps = s->prm.eps;
+  a.gamma = s->prm.gamma;
+  a.tie_rel = s->prm.tie_rel;
+  const int blocks = (s->n_tiles + 3) / 4;
+  int rc = TENO_OK;
+  dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
+    rc = timed(s, 0, st, [&]() {
+      hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value>), dim3(blocks),
+                         dim3(256), 0, st, a);
+    });
+  });
+  return rc;
+}
+
+int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
+                const double* dt, double ca, double cb, double cc, bool rk, hipStream_t st) {
+  FluxArgs a;
+  a.fp = s->fp;
+  a.nbinfo = s->nbinfo;
+  a.geo = s->geo;
+  a.Un = Un;
+  a.Uk = Uk;
+  a.out = out;
+  a.dt = dt;
+  a.ca = ca;
+  a.cb = cb;
+  a.cc = cc;
+  a.gamma = s->prm.gamma;
+  a.n_cell = s->n_cell;
+  a.n_pad = s->n_pad;
+  const int blocks = (s->n_cell + 255) / 256;
+  int rc = TENO_OK;
+  auto go = [&](auto NQ) {
+    rc = timed(s, 1, st, [&]() {
+      if (rk)
+        hipLaunchKernelGGL((k_flux_update<decltype(NQ)::value, true>), dim3(blocks), dim3(256), 0,
+                           st, a);
+      else
+        hipLaunchKernelGGL((k_flux_update<decltype(NQ)::value, false>), dim3(blocks), dim3(256), 0,
+                           st, a);
+    });
+  };
+  if (s->d.nq == 2) go(IC<2>{});
+  else go(IC<3>{});
+  return rc;
+}
+
+int launch_dt(teno_solver* s, const double* U, double cfl, double* dt, hipStream_t st) {
+  return timed(s, 2, st, [&]() {
+    hipLaunchKernelGGL(k_dt_partial, dim3(s->n_dtblk), dim3(256), 0, st, U, s->geo, s->n_cell,
+                       s->prm.gamma, s->dtpart);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, st, s->dtpart, s->n_dtblk, cfl, dt);
+  });
+}
+
+// U_bar = scale * dt_scale * (dR/dU)^T lam + beta * extra, selection frozen.
+int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
+               const double* scale_dev, double scale, const double* extra, double beta,
+               double* out, hipStream_t st) {
+  int rc = launch_reconstruct(s, U, const_cast<uint16_t*>(flags), true, st);
+  if (rc) return rc;
+  AdjArgs fa;
+  fa.fp = s->fp;
+  fa.nbinfo = s->nbinfo;
+  fa.geo = s->geo;
+  fa.lam = lam;
+  fa.scale_dev = scale_dev;
+  fa.scale = scale;
+  fa.fpbar = s->fpbar;
+  fa.gamma = s->prm.gamma;
+  fa.n_cell = s->n_cell;
+  fa.n_pad = s->n_pad;
+  const int cblocks = (s->n_cell + 255) / 256;
+  AdjReconArgs ra;
+  ra.fpbar = s->fpbar;
+  ra.flags = flags;
+  ra.M = s->M;
+  ra.dbar = s->dbar;
+  ra.own = s->own;
+  ra.n_cell = s->n_cell;
+  ra.n_tiles = s->n_tiles;
+  ra.n_pad = s->n_pad;
+  const int tblocks = (s->n_tiles + 3) / 4;
+  dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
+    rc = timed(s, 3, st, [&]() {
+      hipLaunchKernelGGL((k_adj_face<decltype(NQ)::value>), dim3(cblocks), dim3(256), 0, st, fa);
+      hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
+                         dim3(256), 0, st, ra);
+      hipLaunchKernelGGL(k_adj_gather, dim3(cblocks), dim3(256), 0, st, s->own, s->dbar,
+                         s->rev_ptr, s->rev_ent, s->d.rows4 * 4, s->n_cell, s->n_pad, extra, beta,
+                         out);
+    });
+  });
+  return rc;
+}
+
+int lincomb(teno_solver* s, double* out, double a1, const double* x1, double a2, const double* x2,
+            double a3, const double* x3, hipStream_t st) {
+  const long n = (long)s->n_cell * 4;
+  return timed(s, 3, st, [&]() {
+    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, a1,
+                       x1, a2, x2, a3, x3, n);
+  });
+}
+
+int check_solver(teno_solver* s) {
+  if (!s) return fail(TENO_EARG, "null solver");
+  return TENO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* teno_last_error(void) { return teno::last_error(); }
+
+void teno_default_params(teno_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->order = 5;
+  p->n_quad = 0;
+  p->variant = 0;
+  p->power = 6;
+  p->ct = 1e-6;
+  p->eps = 1e-12;
+  p->gamma = 1.4;
+  p->tie_rel = 1e-10;
+  p->fallback = 0;
+  p->reorder = 1;
+  p->n_threads = 0;
+}
+
+int teno_mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
+                     const double* period, teno_mesh** out) {
+  if (!out) return fail(TENO_EARG, "null output");
+  *out = nullptr;
+  teno_mesh* m = new (std::nothrow) teno_mesh();
+  if (!m) return fail(TENO_ENOMEM, "host allocation failed");
+  int rc = mesh_create(n_vert, xy, n_cell, tri, period, m->m);
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return TENO_OK;
+}
+
+int teno_mesh_setup(teno_mesh* m, const teno_params* p) {
+  if (!m || !p) return fail(TENO_EARG, "null argument");
+  try {
+    return mesh_setup(m->m, *p);
+  } catch (const std::bad_alloc&) {
+    return fail(TENO_ENOMEM, "host allocation failed during set-up");
+  }
+}
+
+int teno_mesh_info(const teno_mesh* m, teno_info* out) {
+  if (!m || !out) return fail(TENO_EARG, "null argument");
+  const Mesh& x = m->m;
+  std::memset(out, 0, sizeof(*out));
+  out->n_cell = x.nc;
+  out->n_face = x.nf;
+  if (x.ready) {
+    out->order = x.d.order;
+    out->n_quad = x.d.nq;
+    out->n_coef_large = x.d.nu;
+    out->rows_large = x.d.nl;
+    out->n_coef_small = kSmallCoef;
+    out->rows_small = kSmallRows;
+    out->matrix_doubles_per_cell = x.d.J;
+    out->min_rcond = x.min_rcond;
+  }
+  return TENO_OK;
+}
+
+int teno_mesh_permutation(const teno_mesh* m, int32_t* perm) {
+  if (!m || !perm) return fail(TENO_EARG, "null argument");
+  if (!m->m.ready) return fail(TENO_EARG, "teno_mesh_setup not called");
+  std::memcpy(perm, m->m.perm.data(), sizeof(int32_t) * m->m.nc);
+  return TENO_OK;
+}
+
+int teno_mesh_stencil(const teno_mesh* m, int32_t cell, int32_t k, int32_t* members) {
+  if (!m || !members) return fail(TENO_EARG, "null argument");
+  const Mesh& x = m->m;
+  if (!x.ready) return fail(TENO_EARG, "teno_mesh_setup not called");
+  if (cell < 0 || cell >= x.nc || k < 0 || k > 3) return fail(TENO_EARG, "cell or stencil out of range");
+  const int t = x.inv[cell];
+  const int row0 = k == 3 ? 3 * kSmallRows : k * kSmallRows;
+  const int nrow = k == 3 ? x.d.nl : kSmallRows;
+  for (int s = 0; s < nrow; ++s) members[s] = x.perm[x.idx[packed_idx_index(x, t, row0 + s)]];
+  return nrow;
+}
+
+int teno_mesh_lsq_operator(const teno_mesh* m, int32_t cell, int32_t k, double* M) {
+  if (!m || !M) return fail(TENO_EARG, "null argument");
+  const Mesh& x = m->m;
+  if (!x.ready) return fail(TENO_EARG, "teno_mesh_setup not called");
+  if (cell < 0 || cell >= x.nc || k < 0 || k > 3) return fail(TENO_EARG, "cell or stencil out of range");
+  const int t = x.inv[cell];
+  const bool big = k == 3;
+  const int nrow = big ? x.d.nl : kSmallRows, nco = big ? x.d.nu : kSmallCoef;
+  const int j0 = big ? 3 * kSmallCoef * kSmallRows : k * kSmallCoef * kSmallRows;
+  for (int l = 0; l < nco; ++l)
+    for (int s = 0; s < nrow; ++s) M[(size_t)l * nrow + s] = x.M[packed_M_index(x, t, j0 + s * nco + l)];
+  return nrow;
+}
+
+void teno_mesh_destroy(teno_mesh* m) { delete m; }
+
+int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out) {
+  if (!mesh || !out) return fail(TENO_EARG, "null argument");
+  *out = nullptr;
+  const Mesh& m = mesh->m;
+  if (!m.ready) return fail(TENO_EARG, "teno_mesh_setup not called");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(TENO_EHIP, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(TENO_EARG, "device out of range");
+  bool ok_combo = dispatch(m.d.order, m.d.nq, [](auto, auto) {});
+  if (!ok_combo) return fail(TENO_EARG, "unsupported order / face-point count");
+  DeviceScope ds(device);
+  if (!ds.ok) return fail(TENO_EHIP, "hipSetDevice failed");
+  teno_solver* s = new (std::nothrow) teno_solver();
+  if (!s) return fail(TENO_ENOMEM, "host allocation failed");
+  s->device = device;
+  s->d = m.d;
+  s->prm = m.prm;
+  s->n_cell = m.nc;
+  s->n_pad = m.n_pad;
+  s->n_tiles = m.n_tiles;
+  s->n_dtblk = (m.nc + 255) / 256;
+  const size_t np = m.n_pad, nc = m.nc;
+  int rc = TENO_OK;
+  auto A = [&](auto& p, size_t n) {
+    if (rc == TENO_OK) rc = s->alloc(p, n);
+  };
+  A(s->idx, m.idx.size() / 4);
+  A(s->M, m.M.size() / 2);
+  A(s->nbinfo, np);
+  A(s->geo, np * 10);
+  A(s->user_of, np);
+  A(s->rev_ptr, nc + 1);
+  A(s->rev_ent, std::max<size_t>(1, m.rev_ent.size()));
+  A(s->fp, (size_t)3 * m.d.nq * np * 4);
+  A(s->fpbar, (size_t)3 * m.d.nq * np * 4);
+  A(s->dbar, (size_t)m.d.rows4 * 4 * np * 4);
+  A(s->own, np * 4);
+  A(s->W1, nc * 4);
+  A(s->W2, nc * 4);
+  A(s->T0, nc * 4);
+  A(s->T1, nc * 4);
+  A(s->T2, nc * 4);
+  A(s->dtpart, (size_t)s->n_dtblk);
+  A(s->diag, 1);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  struct Up {
+    void* dst;
+    const void* src;
+    size_t n;
+  } ups[] = {{s->idx, m.idx.data(), m.idx.size() * sizeof(int32_t)},
+             {s->M, m.M.data(), m.M.size() * sizeof(double)},
+             {s->nbinfo, m.nbinfo.data(), m.nbinfo.size() * sizeof(int32_t)},
+             {s->geo, m.geo.data(), m.geo.size() * sizeof(double)},
+             {s->user_of, m.user_of.data(), m.user_of.size() * sizeof(int32_t)},
+             {s->rev_ptr, m.rev_ptr.data(), m.rev_ptr.size() * sizeof(int32_t)},
+             {s->rev_ent, m.rev_ent.data(), m.rev_ent.size() * sizeof(int32_t)}};
+  for (auto& u : ups) {
+    if (u.n == 0) continue;
+    hipError_t e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete s;
+      return hip_fail(e, "hipMemcpy upload");
+    }
+  }
+  hipLaunchKernelGGL(k_diag_reset, dim3(1), dim3(64), 0, 0, s->diag);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "solver initialisation");
+  }
+  *out = s;
+  return TENO_OK;
+}
+
+void teno_solver_destroy(teno_solver* s) {
+  if (!s) return;
+  DeviceScope ds(s->device);
+  delete s;
+}
+
+int teno_reconstruct(teno_solver* s, const double* U, double* face_states, uint16_t* flags,
+                     void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U) return fail(TENO_EARG, "null state");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = launch_reconstruct(s, U, flags, false, st);
+  if (rc) return rc;
+  if (face_states) {
+    hipError_t e = hipMemcpy2DAsync(face_states, (size_t)s->n_cell * 32, s->fp,
+                                    (size_t)s->n_pad * 32, (size_t)s->n_cell * 32,
+                                    (size_t)3 * s->d.nq, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
+  }
+  return TENO_OK;
+}
+
+int teno_residual(teno_solver* s, const double* U, double* R, uint16_t* flags, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U || !R) return fail(TENO_EARG, "null state");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = launch_reconstruct(s, U, flags, false, st);
+  if (rc) return rc;
+  return launch_flux(s, U, U, R, nullptr, 0, 0, 0, false, st);
+}
+
+int teno_residual_frozen(teno_solver* s, const double* U, double* R, const uint16_t* flags,
+                         void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U || !R || !flags) return fail(TENO_EARG, "null argument");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = launch_reconstruct(s, U, const_cast<uint16_t*>(flags), true, st);
+  if (rc) return rc;
+  return launch_flux(s, U, U, R, nullptr, 0, 0, 0, false, st);
+}
+
+int teno_max_dt(teno_solver* s, const double* U, double cfl, double* dt_dev, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U || !dt_dev) return fail(TENO_EARG, "null argument");
+  if (!(cfl > 0.0)) return fail(TENO_EARG, "cfl must be positive");
+  DeviceScope ds(s->device);
+  return launch_dt(s, U, cfl, dt_dev, (hipStream_t)stream);
+}
+
+static const double kStageA[3] = {1.0, 0.75, 1.0 / 3.0};
+static const double kStageB[3] = {0.0, 0.25, 2.0 / 3.0};
+static const double kStageC[3] = {1.0, 0.25, 2.0 / 3.0};
+
+static int stage_impl(teno_solver* s, int k, const double* Un, const double* Uk, double* Uk1,
+                      const double* dt, uint16_t* flags, bool frozen, hipStream_t st) {
+  int rc = launch_reconstruct(s, Uk, flags, frozen, st);
+  if (rc) return rc;
+  return launch_flux(s, Un, Uk, Uk1, dt, kStageA[k], kStageB[k], kStageC[k], true, st);
+}
+
+int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk, double* Uk1,
+                  const double* dt_dev, uint16_t* flags, int32_t frozen, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (k < 0 || k > 2) return fail(TENO_EARG, "stage must be 0, 1 or 2");
+  if (!Un || !Uk || !Uk1 || !dt_dev) return fail(TENO_EARG, "null argument");
+  if (frozen && !flags) return fail(TENO_EARG, "frozen selection needs flags");
+  if (k == 0 && Uk != Un) return fail(TENO_EARG, "stage 0 needs Uk == Un");
+  if (Uk1 == Uk && Uk != Un) return fail(TENO_EARG, "Uk1 must not alias Uk");
+  DeviceScope ds(s->device);
+  return stage_impl(s, k, Un, Uk, Uk1, dt_dev, flags, frozen != 0, (hipStream_t)stream);
+}
+
+int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flags3,
+                 int32_t frozen, double* stages, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U || !dt_dev) return fail(TENO_EARG, "null argument");
+  if (frozen && !flags3) return fail(TENO_EARG, "frozen selection needs flags3");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)s->n_cell;
+  const size_t nb = n * 4 * sizeof(double);
+  auto fl = [&](int k) { return flags3 ? flags3 + (size_t)k * n : nullptr; };
+  if (stages) {
+    hipError_t e = hipMemcpyAsync(stages, U, nb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  int rc = stage_impl(s, 0, U, U, s->W1, dt_dev, fl(0), frozen != 0, st);
+  if (rc) return rc;
+  if (stages) {
+    hipError_t e = hipMemcpyAsync(stages + n * 4, s->W1, nb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  rc = stage_impl(s, 1, U, s->W1, s->W2, dt_dev, fl(1), frozen != 0, st);
+  if (rc) return rc;
+  if (stages) {
+    hipError_t e = hipMemcpyAsync(stages + 2 * n * 4, s->W2, nb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  return stage_impl(s, 2, U, s->W2, U, dt_dev, fl(2), frozen != 0, st);
+}
+
+int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
+                      double* U_bar, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U || !flags || !lam || !U_bar) return fail(TENO_EARG, "null argument");
+  if (U_bar == lam) return fail(TENO_EARG, "U_bar must not alias lam");
+  DeviceScope ds(s->device);
+  return launch_vjp(s, U, flags, lam, nullptr, 1.0, nullptr, 0.0, U_bar, (hipStream_t)stream);
+}
+
+int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags3,
+                     const double* dt_dev, const double* lam_out, double* lam_in, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!stages || !flags3 || !dt_dev || !lam_out || !lam_in) return fail(TENO_EARG, "null argument");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)s->n_cell;
+  const double* U0 = stages;
+  const double* U1 = stages + n * 4;
+  const double* U2 = stages + 2 * n * 4;
+  // U' = 1/3 U0 + 2/3 U2 + 2/3 dt R(U2)   ->  T2 = lam_2 (adjoint of U2)
+  int rc = launch_vjp(s, U2, flags3 + 2 * n, lam_out, dt_dev, 2.0 / 3.0, lam_out, 2.0 / 3.0,
+                      s->T2, st);
+  if (rc) return rc;
+  // U2 = 3/4 U0 + 1/4 U1 + 1/4 dt R(U1)  ->  T1 = lam_1
+  rc = launch_vjp(s, U1, flags3 + n, s->T2, dt_dev, 0.25, s->T2, 0.25, s->T1, st);
+  if (rc) return rc;
+  // U1 = U0 + dt R(U0)                   ->  T0 = lam_1 + dt R'(U0)^T lam_1
+  rc = launch_vjp(s, U0, flags3, s->T1, dt_dev, 1.0, s->T1, 1.0, s->T0, st);
+  if (rc) return rc;
+  return lincomb(s, lam_in, 1.0 / 3.0, lam_out, 0.75, s->T2, 1.0, s->T0, st);
+}
+
+int teno_diagnostics(teno_solver* s, teno_diag* out, int32_t reset, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!out) return fail(TENO_EARG, "null argument");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  DevDiag h;
+  hipError_t e = hipMemcpyAsync(&h, s->diag, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics read");
+  out->nonphysical = (int64_t)h.nonphysical;
+  out->near_ties = (int64_t)h.near_ties;
+  out->fallbacks = (int64_t)h.fallbacks;
+  out->first_bad_cell = h.first_bad == LLONG_MAX ? -1 : (int64_t)h.first_bad;
+  if (reset) {
+    hipLaunchKernelGGL(k_diag_reset, dim3(1), dim3(64), 0, st, s->diag);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "diagnostics reset");
+  }
+  return TENO_OK;
+}
+
+int teno_profile_enable(teno_solver* s, int32_t on) {
+  if (int rc = check_solver(s)) return rc;
+  s->prof = on != 0;
+  return TENO_OK;
+}
+
+int teno_profile_read(teno_solver* s, double* ms, int64_t* launches, int32_t reset) {
+  if (int rc = check_solver(s)) return rc;
+  DeviceScope ds(s->device);
+  for (auto& e : s->evs) {
+    hipError_t r = hipEventSynchronize(e.b);
+    if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e.a, e.b);
+    s->prof_ms[e.kind] += t;
+    s->prof_n[e.kind] += 1;
+    s->pool.push_back({e.a, e.b});
+  }
+  s->evs.clear();
+  for (int k = 0; k < 4; ++k) {
+    if (ms) ms[k] = s->prof_ms[k];
+    if (launches) launches[k] = s->prof_n[k];
+    if (reset) {
+      s->prof_ms[k] = 0;
+      s->prof_n[k] = 0;
+    }
+  }
+  return TENO_OK;
+}
+
+}  // extern "C"

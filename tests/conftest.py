@@ -9,6 +9,9 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # load torch (and its HIP runtime) before any native library of this repo
+    import torch  # noqa: F401
+
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device)")
     config.addinivalue_line("markers", "slow: long-running CPU test")
 

@@ -1,0 +1,321 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars (FP64 throughout):
+  * selection flags bit-exact, except (cell, variable) pairs the oracle
+    reports as near ties (|chi/C_T - 1| <= 1e-10), which are counted;
+  * face-point states and stage states: max_i |x - y| <= 1e-12 max_i |y|
+    per conservative variable;
+  * residual: max |R_gpu - R_oracle| <= 1e-12 * S, where S is the flux scale
+    max_i sum_faces |A| |F(U_i) . n| / |V_i| (R is a difference of O(1/h)
+    face terms, so its own size is not the right reference).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2105_02127_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def teno():
+    from paper_2105_02127_amd import teno as t
+    t.load()
+    return t
+
+
+class Case:
+    """One mesh + state on both sides (oracle in user order, GPU internal)."""
+
+    def __init__(self, teno, oracle_mod, torch, n, seed, order, ic="random_lines", fallback=1,
+                 oracle_all=True, variant=0):
+        print(f"[case] n={n} seed={seed} order={order} ic={ic} fallback={fallback}", flush=True)
+        self.m = inputs.jittered_periodic_mesh(n, seed)
+        self.U = inputs.make_state(self.m, ic)
+        self.lm = teno.Mesh(self.m.xy, self.m.tri).setup(order=order, fallback=fallback,
+                                                         variant=variant)
+        self.sv = teno.Solver(self.lm)
+        self.om = oracle_mod.OracleMesh(self.m.xy, self.m.tri)
+        self.om.setup(oracle_mod.params(order=order, fallback=fallback, variant=variant),
+                      all_cells=oracle_all)
+        self.perm = self.lm.perm
+        self.torch = torch
+        self.Ud = torch.as_tensor(self.U[self.perm], device="cuda")
+
+    def dev(self, a_user):
+        return self.torch.as_tensor(np.ascontiguousarray(a_user[self.perm]), device="cuda")
+
+    def host_user(self, t):
+        a = t.cpu().numpy()
+        out = np.empty_like(a)
+        out[self.perm] = a
+        return out
+
+    def flags_user(self, t):
+        return self.host_user(t).view(np.uint16)
+
+    def flux_scale(self):
+        area, _, _ = self.om.geometry()
+        f = self.om.faces()
+        U = self.U
+        g = 1.4
+        r, mx, my, e = U.T
+        vx, vy = mx / r, my / r
+        p = (g - 1) * (e - 0.5 * r * (vx * vx + vy * vy))
+        acc = np.zeros(len(U))
+        for side in ("L", "R"):
+            c = f[side]
+            un = vx[c] * f["normal"][:, 0] + vy[c] * f["normal"][:, 1]
+            Fm = np.abs(np.stack([r[c] * un, mx[c] * un + p[c] * f["normal"][:, 0],
+                                  my[c] * un + p[c] * f["normal"][:, 1], un * (e[c] + p[c])], 1))
+            np.add.at(acc, c, f["length"] * Fm.max(1))
+        return float((acc / area).max())
+
+
+def assert_states(x, y, rel=REL, what="state"):
+    x = np.asarray(x).reshape(-1, 4)
+    y = np.asarray(y).reshape(-1, 4)
+    for v in range(4):
+        err = np.abs(x[:, v] - y[:, v]).max()
+        ref = np.abs(y[:, v]).max()
+        assert err <= rel * ref, f"{what} variable {v}: max err {err:.3e} vs {rel:.0e} * {ref:.3e}"
+
+
+def flag_mismatch(gpu, orc):
+    """Number of (cell, variable) nibbles that differ."""
+    d = np.asarray(gpu, dtype=np.uint16) ^ np.asarray(orc, dtype=np.uint16)
+    return int(sum(((d >> (4 * v)) & 0xF != 0).sum() for v in range(4)))
+
+
+def check_flags(gpu, orc, orc_diag):
+    bad = flag_mismatch(gpu, orc)
+    assert bad <= orc_diag["near_ties"], f"{bad} flag nibbles differ, oracle near ties {orc_diag['near_ties']}"
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("order,n,seed", [(3, 13, 11), (4, 16, 12), (5, 17, 13), (6, 20, 14)])
+def test_reconstruction_and_residual(teno, oracle_mod, torch_cuda, order, n, seed):
+    c = Case(teno, oracle_mod, torch_cuda, n, seed, order)
+    ores = c.om.residual(c.U, want_fp=True)
+    flags = c.sv.empty_flags()
+    fs = c.sv.reconstruct(c.Ud, flags=flags)
+    torch_cuda.cuda.synchronize()
+    fs_user = np.empty((c.m.n_cell, fs.shape[0], 4))
+    fs_user[c.perm] = fs.permute(1, 0, 2).cpu().numpy()
+    oracle_fp = ores["fp"].reshape(c.m.n_cell, -1, 4)
+    check_flags(c.flags_user(flags), ores["flags"], ores["diag"])
+    assert_states(fs_user, oracle_fp, what="face states")
+    c.sv.diagnostics(reset=True)            # the counters accumulate per call
+    R = c.sv.residual(c.Ud, flags=flags)
+    torch_cuda.cuda.synchronize()
+    err = np.abs(c.host_user(R) - ores["R"]).max()
+    assert err <= REL * c.flux_scale(), (err, c.flux_scale())
+    d = c.sv.diagnostics(reset=True)
+    od = c.om.residual(c.U)["diag"]
+    assert d["nonphysical"] == od["nonphysical"] and d["fallbacks"] == od["fallbacks"]
+    assert d["first_bad_cell"] == od["first_bad_cell"]
+
+
+def test_smooth_wave_all_large_stencil(teno, oracle_mod, torch_cuda):
+    w = inputs.WORKLOADS[1]
+    c = Case(teno, oracle_mod, torch_cuda, w["n"], w["seed"], w["order"], ic="smooth_wave",
+             fallback=0)
+    flags = c.sv.empty_flags()
+    c.sv.residual(c.Ud, flags=flags)
+    assert (c.flags_user(flags) == 0x8888).all()
+    assert c.sv.diagnostics(reset=True)["nonphysical"] == 0
+
+
+def test_trajectory_smooth_wave_10_steps(teno, oracle_mod, torch_cuda):
+    """The small smooth workload: 10 SSP-RK3 steps, compared after every stage."""
+    torch = torch_cuda
+    w = inputs.WORKLOADS[1]
+    c = Case(teno, oracle_mod, torch, w["n"], w["seed"], w["order"], ic="smooth_wave", fallback=0)
+    U = c.U.copy()
+    Ud = c.Ud.clone()
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    stages = torch.empty((3, c.m.n_cell, 4), dtype=torch.float64, device="cuda")
+    flags3 = c.sv.empty_flags(3)
+    for step in range(w["steps"]):
+        c.sv.max_dt(Ud, 0.4, dt)
+        dto = c.om.dt(U, 0.4)
+        assert abs(dt.item() - dto) <= 1e-14 * dto
+        # both sides advance with the oracle's dt
+        dt.fill_(dto)
+        ref = c.om.rk_step(U, dto, want_stages=True)
+        c.sv.rk_step(Ud, dt, flags3=flags3, stages=stages)
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert_states(c.host_user(stages[k]), ref["stages"][k], what=f"step {step} stage {k}")
+            check_flags(c.flags_user(flags3[k]), ref["flags"][k], ref["diag"])
+        U = ref["U"]
+        assert_states(c.host_user(Ud), U, what=f"step {step}")
+
+
+@pytest.mark.parametrize("order", [3, 5, 6])
+def test_rk_stages_random_lines(teno, oracle_mod, torch_cuda, order):
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 18, 40 + order, order)
+    dto = c.om.dt(c.U, 0.4)
+    dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
+    ref = c.om.rk_step(c.U, dto, want_stages=True)
+    Ud = c.Ud.clone()
+    stages = torch.empty((3, c.m.n_cell, 4), dtype=torch.float64, device="cuda")
+    flags3 = c.sv.empty_flags(3)
+    c.sv.rk_step(Ud, dt, flags3=flags3, stages=stages)
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert_states(c.host_user(stages[k]), ref["stages"][k], what=f"stage {k}")
+        check_flags(c.flags_user(flags3[k]), ref["flags"][k], ref["diag"])
+    assert_states(c.host_user(Ud), ref["U"], what="U^{n+1}")
+    # the same step through the stage-by-stage entry point
+    U1 = c.sv.empty_state()
+    U2 = c.sv.empty_state()
+    U3 = c.sv.empty_state()
+    c.sv.rk_stage(0, c.Ud, c.Ud, U1, dt)
+    c.sv.rk_stage(1, c.Ud, U1, U2, dt)
+    c.sv.rk_stage(2, c.Ud, U2, U3, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(U3, Ud)
+
+
+def test_frozen_residual_and_linear_variant(teno, oracle_mod, torch_cuda):
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 16, 51, 4)
+    base = c.om.residual(c.U)
+    fl = c.dev(base["flags"].view(np.int16))
+    U2 = c.U * (1.0 + 1e-3 * np.random.default_rng(0).normal(size=c.U.shape))
+    ref = c.om.residual(U2, frozen_flags=base["flags"])
+    R = c.sv.residual_frozen(c.dev(U2), fl)
+    torch.cuda.synchronize()
+    assert np.abs(c.host_user(R) - ref["R"]).max() <= REL * c.flux_scale()
+    lin = Case(teno, oracle_mod, torch, 16, 51, 4, variant=1)
+    flags = lin.sv.empty_flags()
+    R = lin.sv.residual(lin.Ud, flags=flags)
+    ref = lin.om.residual(lin.U)
+    torch.cuda.synchronize()
+    # large stencil everywhere except cells that fell back to first order
+    np.testing.assert_array_equal(lin.flags_user(flags), ref["flags"])
+    assert set(np.unique(ref["flags"]).tolist()) <= {0, 0x8888}
+    assert np.abs(lin.host_user(R) - ref["R"]).max() <= REL * lin.flux_scale()
+
+
+def test_deterministic_and_conservative(teno, oracle_mod, torch_cuda):
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 24, 61, 5, oracle_all=False)
+    R1 = c.sv.residual(c.Ud)
+    R2 = c.sv.residual(c.Ud)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2)
+    area, _, _ = c.om.geometry()
+    a = torch.as_tensor(area[c.perm], device="cuda")
+    tot = (a[:, None] * R1).sum(0).cpu().numpy()
+    assert np.abs(tot).max() <= 1e-13 * (a[:, None] * R1).abs().sum(0).max().item()
+
+
+def test_dt_matches_oracle(teno, oracle_mod, torch_cuda):
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 21, 71, 3, oracle_all=False)
+    dt = c.sv.max_dt(c.Ud, 0.4)
+    assert dt.item() == pytest.approx(c.om.dt(c.U, 0.4), rel=1e-14)
+
+
+@pytest.mark.parametrize("order", [3, 4, 6])
+def test_vjp_residual_matches_oracle(teno, oracle_mod, torch_cuda, order):
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 14, 80 + order, order)
+    flags = c.om.residual(c.U)["flags"]
+    lam = np.random.default_rng(order).normal(size=c.U.shape)
+    ref = c.om.vjp(c.U, flags, lam)
+    got = c.sv.vjp_residual(c.Ud, c.dev(flags.view(np.int16)), c.dev(lam))
+    torch.cuda.synchronize()
+    assert_states(c.host_user(got), ref, rel=1e-11, what="U_bar")
+
+
+def test_vjp_rk_step_matches_oracle(teno, oracle_mod, torch_cuda):
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 14, 91, 4)
+    dto = c.om.dt(c.U, 0.4)
+    base = c.om.rk_step(c.U, dto, want_stages=True)
+    lam = np.random.default_rng(1).normal(size=c.U.shape)
+    ref = c.om.vjp_rk_step(base["stages"], base["flags"], dto, lam)
+    st = torch.stack([c.dev(base["stages"][k]) for k in range(3)]).contiguous()
+    f3 = torch.stack([c.dev(base["flags"][k].view(np.int16)) for k in range(3)]).contiguous()
+    dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
+    got = c.sv.vjp_rk_step(st, f3, dt, c.dev(lam))
+    torch.cuda.synchronize()
+    assert_states(c.host_user(got), ref, rel=1e-11, what="lam_in")
+
+
+# --------------------------------------------------------------------------
+# full-size workloads: sampled cells the oracle computes one by one
+# --------------------------------------------------------------------------
+def _sampled(teno, oracle_mod, torch, key, n_sample=160):
+    w, m, U = inputs.make_workload(key)
+    print(f"[full-size] {w['name']} cells={m.n_cell}", flush=True)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1)
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    om = oracle_mod.OracleMesh(m.xy, m.tri)
+    om.setup(oracle_mod.params(order=w["order"], fallback=1), all_cells=False)
+    rng = np.random.default_rng(key)
+    cells = np.unique(np.concatenate([rng.integers(0, m.n_cell, n_sample),
+                                      perm[-5:], perm[:3]]))       # include the ragged tail
+    Ud = torch.as_tensor(U[perm], device="cuda")
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(m.n_cell)
+    flags = sv.empty_flags()
+    fs = sv.reconstruct(Ud, flags=flags)
+    R = sv.residual(Ud)
+    torch.cuda.synchronize()
+    fp, ofl, _, odg = om.reconstruct_cells(U, cells)
+    got = fs[:, torch.as_tensor(inv[cells], device="cuda")].permute(1, 0, 2).cpu().numpy()
+    assert_states(got, fp.reshape(len(cells), -1, 4), what="face states")
+    gfl = flags.cpu().numpy().view(np.uint16)[inv[cells]]
+    assert flag_mismatch(gfl, ofl) <= odg["near_ties"]
+    Ro, _ = om.residual_cells(U, cells)
+    Rg = R.cpu().numpy()[inv[cells]]
+    assert np.abs(Rg - Ro).max() <= REL * _flux_scale_cells(U, m, om, cells)
+    # conservation over the whole mesh: sum |V_i| R_i cancels to round-off
+    ar, _, _ = om.geometry()
+    aR = torch.as_tensor(ar[perm], device="cuda")[:, None] * R
+    tot = aR.sum(0).cpu().numpy()
+    assert np.abs(tot).max() <= 1e-12 * aR.abs().sum(0).max().item()
+
+
+def _flux_scale_cells(U, m, om, cells):
+    f = om.faces()
+    area, _, _ = om.geometry()
+    cf = f["cell_face"][cells]
+    r, mx, my, e = U[cells].T
+    vx, vy = mx / r, my / r
+    p = 0.4 * (e - 0.5 * r * (vx * vx + vy * vy))
+    acc = np.zeros(len(cells))
+    for k in range(3):
+        nrm = f["normal"][cf[:, k]]
+        un = vx * nrm[:, 0] + vy * nrm[:, 1]
+        Fm = np.abs(np.stack([r * un, mx * un + p * nrm[:, 0], my * un + p * nrm[:, 1],
+                              un * (e + p)], 1)).max(1)
+        acc += f["length"][cf[:, k]] * Fm
+    return float((acc / area[cells]).max())
+
+
+def test_full_size_teno5_lines_sampled(teno, oracle_mod, torch_cuda):
+    _sampled(teno, oracle_mod, torch_cuda, 2)
+
+
+def test_full_size_teno6_wavejump_sampled(teno, oracle_mod, torch_cuda):
+    _sampled(teno, oracle_mod, torch_cuda, 3, n_sample=64)

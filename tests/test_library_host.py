@@ -1,0 +1,114 @@
+"""Host-side checks of libteno (no GPU): exported ABI, set-up parity with the
+oracle (stencil lists exactly, least-squares operators to round-off), error
+paths of mesh creation and set-up."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2105_02127_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def teno():
+    from paper_2105_02127_amd import teno as t
+    t.load()
+    return t
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "teno.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(teno_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(teno):
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = teno.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(teno.SIGNATURES), set(names) ^ set(teno.SIGNATURES)
+
+
+def test_params_struct_layout_matches_header(teno):
+    import ctypes as C
+    assert C.sizeof(teno.Params) == 4 * 4 + 4 * 8 + 4 * 4
+    p = teno.default_params()
+    assert (p.order, p.power, p.ct, p.eps, p.gamma, p.fallback, p.reorder) == (5, 6, 1e-6, 1e-12, 1.4, 0, 1)
+
+
+@pytest.mark.parametrize("n,order,seed", [(12, 3, 1), (12, 4, 2), (14, 5, 3), (16, 6, 4)])
+def test_setup_parity_with_oracle(teno, oracle_mod, n, order, seed):
+    m = inputs.jittered_periodic_mesh(n, seed)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=order)
+    om = oracle_mod.OracleMesh(m.xy, m.tri)
+    om.setup(oracle_mod.params(order=order), all_cells=False)
+    info = lm.info()
+    assert info.n_cell == om.n_cell and info.n_face == om.n_face
+    assert info.rows_large == 2 * (order * (order + 1) // 2) - 1
+    worst = 0.0
+    for i in range(0, om.n_cell, 3):
+        for k in range(4):
+            np.testing.assert_array_equal(lm.stencil(i, k), om.stencil(i, k))
+            Ml = lm.lsq_operator(i, k)
+            Mo, _ = om.lsq_operator(i, k)
+            worst = max(worst, np.abs(Ml - Mo).max() / np.abs(Mo).max())
+    assert worst < 1e-11, worst
+    perm = lm.perm
+    assert sorted(perm.tolist()) == list(range(om.n_cell))
+
+
+def test_user_order_option(teno):
+    m = inputs.jittered_periodic_mesh(10, 5)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=3, reorder=0)
+    np.testing.assert_array_equal(lm.perm, np.arange(m.n_cell))
+
+
+def test_mesh_errors(teno):
+    m = inputs.jittered_periodic_mesh(8, 1)
+    with pytest.raises(teno.TenoError, match="order"):
+        teno.Mesh(m.xy, m.tri).setup(order=7)
+    with pytest.raises(teno.TenoError, match="C_T"):
+        teno.Mesh(m.xy, m.tri).setup(order=3, ct=0.5)
+    with pytest.raises(teno.TenoError, match="too small|candidates"):
+        small = inputs.jittered_periodic_mesh(4, 1)
+        teno.Mesh(small.xy, small.tri).setup(order=6)
+    bad = m.tri.copy()
+    bad[1] = bad[0]
+    with pytest.raises(teno.TenoError, match="non-manifold|open"):
+        teno.Mesh(m.xy, bad)
+    with pytest.raises(teno.TenoError, match="open edge"):
+        teno.Mesh(m.xy, m.tri[:-1])
+    with pytest.raises(teno.TenoError, match="degenerate"):
+        xy = m.xy.copy()
+        xy[m.tri[0, 1]] = xy[m.tri[0, 0]]
+        teno.Mesh(xy, m.tri)
+    # without the periodic wrap a planar mesh has boundary (or folded) edges
+    with pytest.raises(teno.TenoError, match="open edge|non-manifold"):
+        teno.Mesh(m.xy, m.tri, period=None)
+
+
+def test_orientation_fix_matches_oracle(teno, oracle_mod):
+    m = inputs.jittered_periodic_mesh(10, 6)
+    tri = m.tri.copy()
+    tri[::3] = tri[::3][:, [0, 2, 1]]       # clockwise input for a third of the cells
+    lm = teno.Mesh(m.xy, tri).setup(order=4)
+    om = oracle_mod.OracleMesh(m.xy, tri)
+    om.setup(oracle_mod.params(order=4), all_cells=False)
+    for i in range(0, m.n_cell, 7):
+        for k in range(4):
+            np.testing.assert_array_equal(lm.stencil(i, k), om.stencil(i, k))
+
+
+def test_solver_needs_a_device_or_fails_cleanly(teno):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: covered by the gpu tests")
+    m = inputs.jittered_periodic_mesh(8, 1)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=3)
+    with pytest.raises(teno.TenoError):
+        teno.Solver(lm)
