@@ -27,19 +27,24 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, resource_usage: bool = False) -> str:
+def build(verbose: bool = False, resource_usage: bool = False, lib: str = LIB,
+          extra_hip_flags=None) -> str:
+    """Compile libteno.so.  extra_hip_flags (or TENO_HIPCC_EXTRA, space
+    separated) are appended to the HIP compile line."""
     os.makedirs(BUILD, exist_ok=True)
+    extra_hip = list(extra_hip_flags or []) + os.environ.get("TENO_HIPCC_EXTRA", "").split()
     setup_o = os.path.join(BUILD, "setup.o")
     api_o = os.path.join(BUILD, "teno_api.o")
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o], verbose)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
-    _run(["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, "teno_api.hip"), "-o", api_o], verbose)
-    tmp = LIB + ".tmp"
+    _run(["hipcc", *HIP_FLAGS, *extra_hip, *extra, "-c", os.path.join(CSRC, "teno_api.hip"), "-o",
+          api_o], verbose)
+    tmp = lib + ".tmp"
     _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
           setup_o, api_o, "-pthread",
           "-o", tmp], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

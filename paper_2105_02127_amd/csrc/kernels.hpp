@@ -234,8 +234,19 @@ struct Rows {
   }
 };
 
+// Occupancy target of the reconstruction kernel (waves per SIMD); 0 leaves
+// the register budget to the compiler.
+#ifndef TENO_RECON_WAVES_PER_EU
+#define TENO_RECON_WAVES_PER_EU 0
+#endif
+#if TENO_RECON_WAVES_PER_EU > 0
+#define TENO_RECON_ATTR __attribute__((amdgpu_waves_per_eu(TENO_RECON_WAVES_PER_EU)))
+#else
+#define TENO_RECON_ATTR
+#endif
+
 template <int P, int NQ>
-__global__ __launch_bounds__(256) void k_reconstruct(ReconArgs a) {
+__global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a) {
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;

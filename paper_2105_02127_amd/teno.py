@@ -14,7 +14,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libteno.so")
+LIB_PATH = os.environ.get("TENO_LIB", os.path.join(_HERE, "libteno.so"))
 _lib = None
 
 
