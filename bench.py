@@ -88,6 +88,39 @@ def cpu_baseline(mesh, U, order, fallback, steps=1):
             "seconds": t}
 
 
+def adjoint_timing(torch, teno, inputs, steps=200, checkpoint_every=20):
+    """Forward rollout versus checkpointed backward on the adjoint workload
+    (TENO4, 256x256x2 cells, 200 steps, checkpoint every 20)."""
+    from paper_2105_02127_amd import adjoint
+    w, mesh, U0 = inputs.make_workload(4)
+    lm = teno.Mesh(mesh.xy, mesh.tri).setup(order=w["order"], fallback=1)
+    sv = teno.Solver(lm)
+    U0d = torch.as_tensor(U0[lm.perm], device="cuda")
+    center, radius = inputs.adjoint_loss_disc(mesh)
+    v = inputs.unwrapped_vertices(mesh)
+    e1, e2 = v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    wts = torch.as_tensor((area * inputs.disc_mask(mesh, center, radius))[lm.perm], device="cuda")
+    adjoint.forward_rollout(sv, U0d, 5)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    adjoint.forward_rollout(sv, U0d, steps, checkpoint_every=checkpoint_every)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    x = U0d.clone().requires_grad_(True)
+    UT, _ = adjoint.rollout(sv, x, steps, checkpoint_every=checkpoint_every)
+    loss = adjoint.pressure_squared_loss(UT, wts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    return {"workload": w["name"], "n_cell": mesh.n_cell, "steps": steps,
+            "checkpoint_every": checkpoint_every, "forward_s": t_fwd,
+            "backward_s": t_bwd, "adjoint_over_forward": t_bwd / t_fwd,
+            "note": "backward includes recomputing each 20-step segment from its checkpoint"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +131,7 @@ def main():
     ap.add_argument("--fallback", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -191,6 +225,8 @@ def main():
         "diagnostics": diag,
         "setup_s": t_setup,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_timing(torch, teno, inputs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,95 @@
+"""Reverse-mode differentiation of an SSP-RK3 rollout of the TENO residual.
+
+The stencil selection of every stage and the step sizes are frozen at the
+values of the forward pass.  For fixed selection the reconstruction is linear
+in the cell averages, so the step map is differentiable wherever the HLL flux
+is, and its vector-Jacobian product is what `teno_vjp_rk_step` computes on the
+device (HLL Jacobian by forward-mode dual numbers, reconstruction transposed
+by a reverse-stencil gather, no atomics).
+
+Memory: U is checkpointed every `checkpoint_every` steps; the backward pass
+recomputes one segment at a time (its stage states and flags) and walks it
+backwards.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import teno
+
+
+def forward_rollout(solver: "teno.Solver", U0: torch.Tensor, n_steps: int, cfl: float = 0.4,
+                    dts: torch.Tensor | None = None, checkpoint_every: int = 20,
+                    flags_out: torch.Tensor | None = None,
+                    frozen_flags: torch.Tensor | None = None):
+    """Advances U0 by n_steps.  dts (device float64[n_steps]) is computed with
+    the constant-CFL rule when None, otherwise replayed.  flags_out (int16
+    [n_steps, 3, n_cell]) receives every stage's selection; frozen_flags of
+    the same shape replays a recorded selection instead.  Returns (U, dts,
+    checkpoints) where checkpoints[k] is U at step k * checkpoint_every."""
+    U = U0.detach().clone()
+    if dts is None:
+        dts = torch.empty(n_steps, dtype=torch.float64, device=U.device)
+        fixed = False
+    else:
+        fixed = True
+    ckpts = []
+    for s in range(n_steps):
+        if s % checkpoint_every == 0:
+            ckpts.append(U.clone())
+        dt = dts[s:s + 1]
+        if not fixed:
+            solver.max_dt(U, cfl, dt)
+        if frozen_flags is not None:
+            solver.rk_step(U, dt, flags3=frozen_flags[s], frozen=True)
+        else:
+            solver.rk_step(U, dt, flags3=None if flags_out is None else flags_out[s])
+    return U, dts, ckpts
+
+
+class RK3Rollout(torch.autograd.Function):
+    """U_final = rollout(U0); backward gives d(loss)/d(U0) with frozen dt and
+    selection."""
+
+    @staticmethod
+    def forward(ctx, U0, solver, n_steps, cfl, checkpoint_every, dts):
+        U, dts_used, ckpts = forward_rollout(solver, U0, n_steps, cfl, dts, checkpoint_every)
+        if dts is not None:
+            dts_used = dts_used.clone()
+        ctx.solver = solver
+        ctx.n_steps = n_steps
+        ctx.K = checkpoint_every
+        ctx.dts = dts_used
+        ctx.ckpts = ckpts
+        ctx.mark_non_differentiable(dts_used)
+        return U, dts_used
+
+    @staticmethod
+    def backward(ctx, grad_U, grad_dts):
+        sv, n, K = ctx.solver, ctx.n_steps, ctx.K
+        lam = grad_U.detach().contiguous().clone()
+        nc = lam.shape[0]
+        dev = lam.device
+        stages = torch.empty((K, 3, nc, 4), dtype=torch.float64, device=dev)
+        flags = torch.empty((K, 3, nc), dtype=torch.int16, device=dev)
+        for seg in reversed(range(len(ctx.ckpts))):
+            s0 = seg * K
+            s1 = min(n, s0 + K)
+            U = ctx.ckpts[seg].clone()
+            for s in range(s0, s1):     # recompute the segment, keeping its stages
+                sv.rk_step(U, ctx.dts[s:s + 1], flags3=flags[s - s0], stages=stages[s - s0])
+            for s in reversed(range(s0, s1)):
+                sv.vjp_rk_step(stages[s - s0], flags[s - s0], ctx.dts[s:s + 1], lam, lam)
+        return lam, None, None, None, None, None
+
+
+def rollout(solver, U0, n_steps, cfl=0.4, checkpoint_every=20, dts=None):
+    """Differentiable rollout: returns (U_final, dts)."""
+    return RK3Rollout.apply(U0, solver, n_steps, cfl, checkpoint_every, dts)
+
+
+def pressure_squared_loss(U, weights, gamma=1.4):
+    """sum_i w_i p_i^2 with p from the conservative variables."""
+    r, mx, my, e = U[:, 0], U[:, 1], U[:, 2], U[:, 3]
+    p = (gamma - 1.0) * (e - 0.5 * (mx * mx + my * my) / r)
+    return (weights * p * p).sum()

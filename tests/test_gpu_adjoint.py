@@ -1,0 +1,113 @@
+"""Adjoint of the SSP-RK3 rollout on the GPU: against the oracle's composed
+step adjoints, and against central finite differences on the adjoint workload
+(TENO4, 256x256x2 cells, 200 steps, checkpoint every 20, loss = sum |V| p^2
+over a seeded disc of radius 0.1, 32 seeded directions, h = 1e-7)."""
+import numpy as np
+import pytest
+
+from paper_2105_02127_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_rollout_gradient_matches_oracle(oracle_mod, torch_cuda):
+    torch = torch_cuda
+    from paper_2105_02127_amd import adjoint, teno
+    n, order, steps, K = 12, 4, 6, 4
+    m = inputs.jittered_periodic_mesh(n, 101)
+    U0 = inputs.random_lines(m)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=order, fallback=1)
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    om = oracle_mod.OracleMesh(m.xy, m.tri)
+    om.setup(oracle_mod.params(order=order, fallback=1))
+    # oracle forward with its own dt sequence, recording stages and flags
+    U = U0.copy()
+    recs = []
+    for _ in range(steps):
+        dt = om.dt(U, 0.4)
+        r = om.rk_step(U, dt, want_stages=True)
+        recs.append((r["stages"], r["flags"], dt))
+        U = r["U"]
+    w = np.random.default_rng(5).normal(size=U.shape)
+    lam = w.copy()
+    for st, fl, dt in reversed(recs):
+        lam = om.vjp_rk_step(st, fl, dt, lam)
+    # GPU: same dt sequence replayed
+    dts = torch.tensor([d for _, _, d in recs], dtype=torch.float64, device="cuda")
+    U0d = torch.as_tensor(U0[perm], device="cuda").requires_grad_(True)
+    UT, _ = adjoint.rollout(sv, U0d, steps, checkpoint_every=K, dts=dts)
+    wd = torch.as_tensor(w[perm], device="cuda")
+    (UT * wd).sum().backward()
+    g = np.empty_like(U0)
+    g[perm] = U0d.grad.cpu().numpy()
+    Ug = np.empty_like(U0)
+    Ug[perm] = UT.detach().cpu().numpy()
+    for v in range(4):
+        assert np.abs(Ug[:, v] - U[:, v]).max() <= 1e-12 * np.abs(U[:, v]).max()
+        assert np.abs(g[:, v] - lam[:, v]).max() <= 1e-10 * np.abs(lam[:, v]).max(), v
+
+
+def test_adjoint_workload_against_finite_differences(torch_cuda):
+    torch = torch_cuda
+    from paper_2105_02127_amd import adjoint, teno
+    w, m, U0 = inputs.make_workload(4)
+    center, radius = inputs.adjoint_loss_disc(m)
+    steps, K = w["steps"], 20
+    print(f"[adjoint] {w['name']} cells={m.n_cell} steps={steps}", flush=True)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1)
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    vtx = inputs.unwrapped_vertices(m)
+    e1, e2 = vtx[:, 1] - vtx[:, 0], vtx[:, 2] - vtx[:, 0]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    wts = torch.as_tensor((area * inputs.disc_mask(m, center, radius))[perm], device="cuda")
+    U0d = torch.as_tensor(U0[perm], device="cuda")
+    # forward + backward
+    x = U0d.clone().requires_grad_(True)
+    UT, dts = adjoint.rollout(sv, x, steps, checkpoint_every=K)
+    loss = adjoint.pressure_squared_loss(UT, wts)
+    loss.backward()
+    grad = x.grad.detach()
+    # base selection of every stage, to replay (frozen) and to detect flips
+    base_flags = torch.empty((steps, 3, m.n_cell), dtype=torch.int16, device="cuda")
+    UB, _, _ = adjoint.forward_rollout(sv, U0d, steps, dts=dts, flags_out=base_flags)
+    assert torch.equal(UB, UT.detach())
+    L = lambda U: adjoint.pressure_squared_loss(U, wts).item()
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    h = 1e-7
+    worst, flipped, free_ok = 0.0, 0, []
+    fl = torch.empty_like(base_flags)
+    for d in range(32):
+        v = torch.randn(U0d.shape, dtype=torch.float64, device="cuda", generator=gen)
+        ref = (grad * v).sum().item()
+        up, _, _ = adjoint.forward_rollout(sv, U0d + h * v, steps, dts=dts, frozen_flags=base_flags)
+        um, _, _ = adjoint.forward_rollout(sv, U0d - h * v, steps, dts=dts, frozen_flags=base_flags)
+        fd = (L(up) - L(um)) / (2 * h)
+        rel = abs(fd - ref) / abs(ref)
+        worst = max(worst, rel)
+        # free selection: count directions whose perturbed runs flip any flag
+        flips = 0
+        for sgn in (1.0, -1.0):
+            uf, _, _ = adjoint.forward_rollout(sv, U0d + sgn * h * v, steps, dts=dts, flags_out=fl)
+            flips += int((fl != base_flags).sum().item())
+        if flips:
+            flipped += 1
+        else:
+            up2, _, _ = adjoint.forward_rollout(sv, U0d + h * v, steps, dts=dts)
+            um2, _, _ = adjoint.forward_rollout(sv, U0d - h * v, steps, dts=dts)
+            free_ok.append(abs((L(up2) - L(um2)) / (2 * h) - ref) / abs(ref))
+        print(f"[adjoint] dir {d}: vjp {ref:+.10e} fd {fd:+.10e} rel {rel:.2e} flag flips {flips}",
+              flush=True)
+    print(f"[adjoint] worst frozen-selection rel err {worst:.2e}; directions with flips {flipped}/32; "
+          f"free-selection rel errs {['%.1e' % e for e in free_ok]}", flush=True)
+    assert worst < 1e-5
+    assert all(e < 1e-5 for e in free_ok)
