@@ -23,7 +23,6 @@ struct Dims {
   int rows = 0;    // all stencil rows: 3 * 11 small + nl
   int rows4 = 0;   // rows rounded up to a multiple of 4 (int4 loads)
   int J = 0;       // operator entries per cell: 3 * 5 * 11 + nu * nl
-  int J2 = 0;      // J rounded up to pairs (double2 loads)
 };
 
 Dims dims_for(int order, int nq_req);
@@ -56,7 +55,7 @@ struct Mesh {
   // ---- packed device images, internal order, tile-major ----
   int n_pad = 0, n_tiles = 0;
   std::vector<int32_t> idx;     // [n_tiles][rows4][16][4] stencil members (internal)
-  std::vector<double> M;        // [n_tiles][J2][16][2] operator entries
+  std::vector<double> M;        // [n_tiles][J][16] operator entries, cells innermost
   std::vector<int32_t> nbinfo;  // [n_pad][4]: 3 neighbours + packed edge/side bits
   std::vector<double> geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area
   std::vector<int32_t> user_of; // [n_pad] user id (diagnostics)
@@ -71,7 +70,7 @@ struct Mesh {
 // Stencil row order: rows 0..32 small stencils (11 each), then nl large rows.
 inline int64_t packed_M_index(const Mesh& m, int internal, int j) {
   int t = internal / kTile, c = internal % kTile;
-  return (((int64_t)t * m.d.J2 + (j >> 1)) * kTile + c) * 2 + (j & 1);
+  return ((int64_t)t * m.d.J + j) * kTile + c;
 }
 
 inline int64_t packed_idx_index(const Mesh& m, int internal, int row) {

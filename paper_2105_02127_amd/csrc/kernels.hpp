@@ -1,13 +1,18 @@
 // HIP kernels of the TENO residual for gfx950 (MI355X), FP64.
 //
-//   k_reconstruct  one 64-lane wavefront per tile of 16 cells, one lane per
-//                  (cell, conservative variable).  Streams the cell's
-//                  least-squares operators (tile-major, double2 loads, fully
-//                  coalesced), gathers stencil differences, forms the
-//                  coefficients of the three small and the large stencil
-//                  (Sec. 2.2 eqs. 08-10), smoothness indicators (Sec. 2.3),
-//                  strong scale separation and the two-step ENO-like selection
-//                  (Sec. 3.2-3.3), and writes the face Gauss-point states once.
+//   k_reconstruct  one 64-lane wavefront per tile of 16 cells, four lanes per
+//                  cell.  Least-squares phase (Sec. 2.2 eqs. 08-10): the four
+//                  lanes split the coefficient index (lane g owns l = g,
+//                  g+4, ...) and carry all four conservative variables, so
+//                  every operator entry is loaded by exactly one lane and a
+//                  wavefront load moves 512 contiguous bytes; stencil
+//                  differences are gathered one variable per lane and shared
+//                  by DPP quad broadcasts.  Selection phase: DPP quad
+//                  transposes give lane g the full coefficient vector of
+//                  variable g, which then forms the smoothness indicators
+//                  (Sec. 2.3), the strong scale separation and the two-step
+//                  ENO-like selection (Sec. 3.2-3.3), and the face
+//                  Gauss-point states, written once.
 //  k_flux_update   one lane per cell: rotated HLL flux with Einfeldt/Roe wave
 //                  speeds (Sec. 4) on the cell's three faces from its own and
 //                  its neighbours' face states, face quadrature, gather into
@@ -24,6 +29,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.h"
 #include "tables.h"
@@ -179,7 +185,7 @@ __device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, dou
 struct ReconArgs {
   const double* __restrict__ U;        // [n_cell][4]
   const int4* __restrict__ idx;        // [n_tiles][rows4][16] int4
-  const double2* __restrict__ M;       // [n_tiles][J2][16] double2
+  const double* __restrict__ M;        // [n_tiles][J][16]
   double* __restrict__ fp;             // [3 nq][n_pad][4]
   uint16_t* flags;                     // out, or in when frozen
   const int32_t* __restrict__ user_of; // [n_pad]
@@ -209,30 +215,86 @@ __device__ __forceinline__ double quad_form(const double (&B)[N][N], const doubl
   return s;
 }
 
-// Accumulate rows [R0, R1) of the operator stream: row r gathers
-// d = U[member r] - U_0 and adds M[j] d to acc[l] for entry
-// j = J0 + (r - R0) * NC + l (all indices compile-time constants).
-template <int R0, int R1, int J0, int NC>
-struct Rows {
-  template <int G = R0>
-  static __device__ __forceinline__ void run(const double* __restrict__ U,
-                                             const int4* __restrict__ ip,
-                                             const double2* __restrict__ mp, int v, double u0,
-                                             double* acc) {
-    if constexpr (G < R1) {
-      const int4 q = ip[(G >> 2) * kTile];
-      const int id = (G & 3) == 0 ? q.x : ((G & 3) == 1 ? q.y : ((G & 3) == 2 ? q.z : q.w));
-      const double d = U[(size_t)id * 4 + v] - u0;
-#pragma unroll
-      for (int l = 0; l < NC; ++l) {
-        const int j = J0 + (G - R0) * NC + l;
-        const double2 m2 = mp[(j >> 1) * kTile];
-        acc[l] = fma((j & 1) ? m2.y : m2.x, d, acc[l]);
-      }
-      run<G + 1>(U, ip, mp, v, u0, acc);
-    }
+// Broadcast lane K of every group of four lanes (DPP quad permutation).
+template <int K>
+__device__ __forceinline__ double quad_bcast(double x) {
+  constexpr int ctrl = K * 0x55;  // quad_perm(K, K, K, K)
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double pick4(double t0, double t1, double t2, double t3, int g) {
+  return g == 0 ? t0 : (g == 1 ? t1 : (g == 2 ? t2 : t3));
+}
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
   }
-};
+}
+
+// Least-squares phase over NR stencil rows starting at row R0 whose rows
+// carry NC operator entries each, starting at entry J0.  Row r gathers this
+// lane's variable g of member r, forms d = U_member - U_0 for all four
+// variables by quad broadcast, and adds M[l] d to acc[t][v] for the
+// coefficients l = g + 4t this lane owns.  Rows are visited in order, so
+// every coefficient is summed over the rows in the same order as a plain
+// GEMV.
+//
+// Member indices come from LDS (staged once per tile), so a gather waits only
+// on the LDS counter.  The row loop is rolled and walks pairs of rows with
+// two fixed buffers: the loads of the next row are in flight while the
+// current row is accumulated, and no register ever changes role between
+// iterations (a rotating buffer would force a full wait every row; deeper
+// buffering or unrolling lets the compiler raise register use and lose
+// occupancy).
+template <int R0, int NR, int J0, int NC>
+__device__ __forceinline__ void split_rows(const double* __restrict__ U, const int* sidx, int c,
+                                           const double* __restrict__ mp, int g, double u0g,
+                                           double (&acc)[(NC + 3) / 4][4]) {
+  constexpr int NT = (NC + 3) / 4;
+  auto issue = [&](int s, double& x, double (&m)[NT]) {
+    const int r = R0 + s;
+    const int id = sidx[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
+    x = U[(size_t)id * 4 + g];
+    const double* __restrict__ mr = mp + (size_t)(J0 + s * NC) * kTile;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int l = g + 4 * t;
+      m[t] = (4 * t + 3 < NC || l < NC) ? mr[(size_t)l * kTile] : 0.0;
+    }
+  };
+  auto accumulate = [&](double xv, const double (&m)[NT]) {
+    const double x = xv - u0g;
+    const double d[4] = {quad_bcast<0>(x), quad_bcast<1>(x), quad_bcast<2>(x), quad_bcast<3>(x)};
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][v] = fma(m[t], d[v], acc[t][v]);
+  };
+  double xa, xb, ma[NT], mb[NT];
+  issue(0, xa, ma);
+  int s = 0;
+#pragma unroll 1
+  for (; s + 1 < NR; s += 2) {
+    issue(s + 1, xb, mb);
+    accumulate(xa, ma);
+    issue(s + 2 < NR ? s + 2 : NR - 1, xa, ma);  // clamped: stays inside the tile
+    accumulate(xb, mb);
+  }
+  if (s < NR) accumulate(xa, ma);
+}
+
+// Coefficient L of variable g, held by lane L%4 of the quad in slot L/4.
+template <int L, int NT>
+__device__ __forceinline__ double coef_of(const double (&acc)[NT][4], int g) {
+  constexpr int src = L & 3, t = L >> 2;
+  return pick4(quad_bcast<src>(acc[t][0]), quad_bcast<src>(acc[t][1]),
+               quad_bcast<src>(acc[t][2]), quad_bcast<src>(acc[t][3]), g);
+}
 
 // Occupancy target of the reconstruction kernel (waves per SIMD); 0 leaves
 // the register budget to the compiler.
@@ -251,75 +313,93 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
   const int lane = threadIdx.x & 63;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int wave = threadIdx.x >> 6;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  // stage this tile's stencil member indices in LDS ([row4][cell][4] ints)
+  __shared__ int4 sidx4[4][O::ROWS4 * kTile];
+  if (tile < a.n_tiles) {
+    const int4* __restrict__ src = a.idx + (size_t)tile * O::ROWS4 * kTile;
+    for (int i = lane; i < O::ROWS4 * kTile; i += 64) sidx4[wave][i] = src[i];
+  }
+  __syncthreads();
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
-  const int c = lane >> 2, v = lane & 3;
+  const int* sidx = reinterpret_cast<const int*>(sidx4[wave]);
+  const int c = lane >> 2, g = lane & 3;  // g: coefficient group, then variable
   const int cell = tile * kTile + c;
   const bool live = cell < a.n_cell;
-  const double u0 = a.U[(size_t)(live ? cell : 0) * 4 + v];
-  const int4* __restrict__ ip = a.idx + (size_t)tile * O::ROWS4 * kTile + c;
-  const double2* __restrict__ mp = a.M + (size_t)tile * O::J2 * kTile + c;
-
-  // ---- small stencils: rows 0..32, entries 0..164 ----
-  double as0[5] = {0, 0, 0, 0, 0}, as1[5] = {0, 0, 0, 0, 0}, as2[5] = {0, 0, 0, 0, 0};
-  Rows<0, 11, 0, 5>::run(a.U, ip, mp, v, u0, as0);
-  Rows<11, 22, 55, 5>::run(a.U, ip, mp, v, u0, as1);
-  Rows<22, 33, 110, 5>::run(a.U, ip, mp, v, u0, as2);
-
+  const double u0 = a.U[(size_t)(live ? cell : 0) * 4 + g];
+  const double* __restrict__ mp = a.M + (size_t)tile * O::J * kTile + c;
   const bool frozen = a.frozen != 0;
-  unsigned nib = 0;
-  int ties = 0;
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  if (!frozen && a.variant == 0) {
-    g0 = gamma_k(quad_form(SmoothForm<2>::B.v, as0), a.eps, a.power);
-    g1 = gamma_k(quad_form(SmoothForm<2>::B.v, as1), a.eps, a.power);
-    g2 = gamma_k(quad_form(SmoothForm<2>::B.v, as2), a.eps, a.power);
-  }
-  // ---- large stencil: rows 33..33+NL-1 ----
-  double aK[NU];
-#pragma unroll
-  for (int l = 0; l < NU; ++l) aK[l] = 0.0;
-  Rows<33, O::ROWS, 165, NU>::run(a.U, ip, mp, v, u0, aK);
+  const unsigned nib_in = (frozen && live) ? ((a.flags[cell] >> (4 * g)) & 0xFu) : 8u;
 
-  if (frozen) {
-    nib = live ? ((a.flags[cell] >> (4 * v)) & 0xFu) : 8u;
-  } else if (a.variant == 1) {
-    nib = 8u;
-  } else {
-    const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
-    const double ssum = (g0 + g1) + g2;
-    const double chiK = gK / (ssum + gK);
-    const bool tie_on = a.ct > 0.0;
-    if (tie_on && fabs(chiK / a.ct - 1.0) <= a.tie_rel) ++ties;
-    if (chiK >= a.ct) {
-      nib = 8u;
-    } else {
-      const double x0 = g0 / ssum, x1 = g1 / ssum, x2 = g2 / ssum;
-      if (tie_on) {
-        ties += fabs(x0 / a.ct - 1.0) <= a.tie_rel;
-        ties += fabs(x1 / a.ct - 1.0) <= a.tie_rel;
-        ties += fabs(x2 / a.ct - 1.0) <= a.tie_rel;
-      }
-      nib = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
+  // ---- small stencils (rows 0..32, entries 0..164), then step two of the
+  //      selection, which needs only their indicators ----
+  double as[3][5];
+  {
+    double s0[2][4] = {}, s1[2][4] = {}, s2[2][4] = {};
+    split_rows<0, 11, 0, 5>(a.U, sidx, c, mp, g, u0, s0);
+    split_rows<11, 11, 55, 5>(a.U, sidx, c, mp, g, u0, s1);
+    split_rows<22, 11, 110, 5>(a.U, sidx, c, mp, g, u0, s2);
+    static_for<0, 5>([&](auto L) {
+      as[0][L] = coef_of<L, 2>(s0, g);
+      as[1][L] = coef_of<L, 2>(s1, g);
+      as[2][L] = coef_of<L, 2>(s2, g);
+    });
+  }
+  unsigned nsm = nib_in & 7u;
+  int ties_small = 0;
+  double ssum = 0.0;
+  if (!frozen && a.variant == 0) {
+    const double g0 = gamma_k(quad_form(SmoothForm<2>::B.v, as[0]), a.eps, a.power);
+    const double g1 = gamma_k(quad_form(SmoothForm<2>::B.v, as[1]), a.eps, a.power);
+    const double g2 = gamma_k(quad_form(SmoothForm<2>::B.v, as[2]), a.eps, a.power);
+    ssum = (g0 + g1) + g2;
+    const double x0 = g0 / ssum, x1 = g1 / ssum, x2 = g2 / ssum;
+    if (a.ct > 0.0) {
+      ties_small += fabs(x0 / a.ct - 1.0) <= a.tie_rel;
+      ties_small += fabs(x1 / a.ct - 1.0) <= a.tie_rel;
+      ties_small += fabs(x2 / a.ct - 1.0) <= a.tie_rel;
+    }
+    nsm = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
+  }
+  double asm_[5];
+  {
+    const int cnt = (int)(nsm & 1u) + (int)((nsm >> 1) & 1u) + (int)((nsm >> 2) & 1u);
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      double acc = 0.0;
+      if (nsm & 1u) acc += as[0][l];
+      if (nsm & 2u) acc += as[1][l];
+      if (nsm & 4u) acc += as[2][l];
+      asm_[l] = cnt > 0 ? acc / (double)cnt : 0.0;
     }
   }
-  // ---- combined coefficients ----
-  const bool keepK = (nib & 8u) != 0;
-  const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
+
+  // ---- large stencil (rows 33.., entries 165..) ----
+  double aK[NU];
+  {
+    constexpr int NT = (NU + 3) / 4;
+    double sk[NT][4] = {};
+    split_rows<33, O::NL, 165, NU>(a.U, sidx, c, mp, g, u0, sk);
+    static_for<0, NU>([&](auto L) { aK[L] = coef_of<L, NT>(sk, g); });
+  }
+  bool keepK = true;
+  int ties = 0;
+  if (frozen) {
+    keepK = (nib_in & 8u) != 0;
+  } else if (a.variant == 0) {
+    const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
+    const double chiK = gK / (ssum + gK);
+    if (a.ct > 0.0 && fabs(chiK / a.ct - 1.0) <= a.tie_rel) ++ties;
+    keepK = chiK >= a.ct;
+    if (!keepK) ties += ties_small;
+  }
+  unsigned nib = keepK ? 8u : nsm;
   double ab[NU];
 #pragma unroll
-  for (int l = 0; l < NU; ++l) {
-    double sm = 0.0;
-    if (l < 5) {
-      double acc = 0.0;
-      if (nib & 1u) acc += as0[l];
-      if (nib & 2u) acc += as1[l];
-      if (nib & 4u) acc += as2[l];
-      sm = cnt > 0 ? acc / (double)cnt : 0.0;
-    }
-    ab[l] = keepK ? aK[l] : sm;
-  }
-  // ---- face Gauss points ----
+  for (int l = 0; l < NU; ++l) ab[l] = keepK ? aK[l] : (l < 5 ? asm_[l] : 0.0);
+
+  // ---- face Gauss points (variable g of this cell) ----
   double val[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
@@ -330,18 +410,14 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
   }
   // ---- non-physical states (all four lanes of a cell agree) ----
   if (!frozen) {
-    const int base = lane & ~3;
-    const double r0 = __shfl(u0, base + 0), r1 = __shfl(u0, base + 1);
-    const double r2 = __shfl(u0, base + 2), r3 = __shfl(u0, base + 3);
-    const bool avg_ok = physical(r0, r1, r2, r3, a.gamma);
+    const bool avg_ok = physical(quad_bcast<0>(u0), quad_bcast<1>(u0), quad_bcast<2>(u0),
+                                 quad_bcast<3>(u0), a.gamma);
     bool fp_ok = true;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const double s0 = __shfl(val[q], base + 0), s1 = __shfl(val[q], base + 1);
-      const double s2 = __shfl(val[q], base + 2), s3 = __shfl(val[q], base + 3);
-      fp_ok = fp_ok && physical(s0, s1, s2, s3, a.gamma);
-    }
-    if (live && v == 0 && !(avg_ok && fp_ok)) {
+    for (int q = 0; q < NP; ++q)
+      fp_ok = fp_ok && physical(quad_bcast<0>(val[q]), quad_bcast<1>(val[q]),
+                                quad_bcast<2>(val[q]), quad_bcast<3>(val[q]), a.gamma);
+    if (live && g == 0 && !(avg_ok && fp_ok)) {
       atomicAdd(&a.diag->nonphysical, 1ull);
       atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
     }
@@ -349,19 +425,19 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
 #pragma unroll
       for (int q = 0; q < NP; ++q) val[q] = u0;
       nib = 0u;
-      if (live && v == 0) atomicAdd(&a.diag->fallbacks, 1ull);
+      if (live && g == 0) atomicAdd(&a.diag->fallbacks, 1ull);
     }
     if (live && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
   }
   if (live) {
 #pragma unroll
-    for (int q = 0; q < NP; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + v] = val[q];
+    for (int q = 0; q < NP; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + g] = val[q];
   }
   if (!frozen && a.flags) {
-    unsigned f = nib << (4 * v);
+    unsigned f = nib << (4 * g);
     f |= __shfl_xor(f, 1);
     f |= __shfl_xor(f, 2);
-    if (live && v == 0) a.flags[cell] = (uint16_t)f;
+    if (live && g == 0) a.flags[cell] = (uint16_t)f;
   }
 }
 
@@ -572,7 +648,7 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
 struct AdjReconArgs {
   const double* __restrict__ fpbar;
   const uint16_t* __restrict__ flags;
-  const double2* __restrict__ M;
+  const double* __restrict__ M;
   double* __restrict__ dbar;   // [rows4*4][n_pad][4]
   double* __restrict__ own;    // [n_pad][4]
   int n_cell, n_tiles, n_pad;
@@ -601,7 +677,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
 #pragma unroll
     for (int l = 0; l < NU; ++l) ab[l] = fma(FaceBasis<O::R, NQ>::P.v[q][l], gq, ab[l]);
   }
-  const double2* __restrict__ mp = a.M + (size_t)tile * O::J2 * kTile + c;
+  const double* __restrict__ mp = a.M + (size_t)tile * O::J * kTile + c;
   const bool keepK = nib & 8u;
   const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
   double dsum = 0.0;
@@ -615,8 +691,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
 #pragma unroll
       for (int l = 0; l < 5; ++l) {
         const int j = k * 55 + s * 5 + l;
-        const double2 q = mp[(j >> 1) * kTile];
-        d = fma((j & 1) ? q.y : q.x, ab[l], d);
+        d = fma(mp[(size_t)j * kTile], ab[l], d);
       }
       d *= wk;
       dsum += d;
@@ -630,8 +705,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
 #pragma unroll
     for (int l = 0; l < NU; ++l) {
       const int j = 165 + s * NU + l;
-      const double2 q = mp[(j >> 1) * kTile];
-      d = fma((j & 1) ? q.y : q.x, ab[l], d);
+      d = fma(mp[(size_t)j * kTile], ab[l], d);
     }
     d *= wK;
     dsum += d;

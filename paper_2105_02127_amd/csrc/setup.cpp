@@ -44,7 +44,6 @@ Dims dims_for(int order, int nq_req) {
   d.rows = 3 * kSmallRows + d.nl;
   d.rows4 = (d.rows + 3) / 4;
   d.J = 3 * kSmallCoef * kSmallRows + d.nu * d.nl;
-  d.J2 = (d.J + 1) / 2;
   return d;
 }
 
@@ -464,7 +463,7 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   m.n_pad = m.n_tiles * kTile;
   try {
     m.idx.assign((size_t)m.n_tiles * d.rows4 * kTile * 4, 0);
-    m.M.assign((size_t)m.n_tiles * d.J2 * kTile * 2, 0.0);
+    m.M.assign((size_t)m.n_tiles * d.J * kTile, 0.0);
   } catch (...) {
     return fail(TENO_ENOMEM, "host allocation of packed operators failed");
   }

@@ -133,7 +133,6 @@ struct OrderT {
   static constexpr int ROWS = 33 + NL;
   static constexpr int ROWS4 = (ROWS + 3) / 4;
   static constexpr int J = 165 + NU * NL;
-  static constexpr int J2 = (J + 1) / 2;
 };
 
 }  // namespace teno

@@ -65,7 +65,7 @@ struct teno_solver {
   teno_params prm{};
   int n_cell = 0, n_pad = 0, n_tiles = 0;
   int4* idx = nullptr;
-  double2* M = nullptr;
+  double* M = nullptr;
   int4* nbinfo = nullptr;
   double* geo = nullptr;
   int32_t* user_of = nullptr;
@@ -401,7 +401,7 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
     if (rc == TENO_OK) rc = s->alloc(p, n);
   };
   A(s->idx, m.idx.size() / 4);
-  A(s->M, m.M.size() / 2);
+  A(s->M, m.M.size());
   A(s->nbinfo, np);
   A(s->geo, np * 10);
   A(s->user_of, np);
