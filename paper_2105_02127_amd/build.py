@@ -33,9 +33,12 @@ def build(verbose: bool = False, resource_usage: bool = False, lib: str = LIB,
     separated) are appended to the HIP compile line."""
     os.makedirs(BUILD, exist_ok=True)
     extra_hip = list(extra_hip_flags or []) + os.environ.get("TENO_HIPCC_EXTRA", "").split()
+    # layout macros must reach both the host set-up and the kernels
+    layout = [f for f in extra_hip if f.startswith("-DTENO_TILE")]
     setup_o = os.path.join(BUILD, "setup.o")
     api_o = os.path.join(BUILD, "teno_api.o")
-    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o], verbose)
+    _run(["g++", *HOST_FLAGS, *layout, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o],
+         verbose)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
     _run(["hipcc", *HIP_FLAGS, *extra_hip, *extra, "-c", os.path.join(CSRC, "teno_api.hip"), "-o",
           api_o], verbose)

@@ -9,9 +9,15 @@
 
 namespace teno {
 
-// Cells per wavefront tile: one 64-lane wavefront handles 16 cells x 4
-// conservative variables in the reconstruction kernel.
-constexpr int kTile = 16;
+// Cells per wavefront tile of the reconstruction kernel (16 or 8): the 64
+// lanes of a wavefront give each cell 64 / kTile lanes.  Host packing and
+// device kernels must agree, so both compilers see the same macro.
+#ifndef TENO_TILE
+#define TENO_TILE 16
+#endif
+constexpr int kTile = TENO_TILE;
+constexpr int kLanesPerCell = 64 / kTile;
+static_assert(kTile == 16 || kTile == 8, "tile must hold 16 or 8 cells");
 
 // Sizes of one order (Sec. 2.2 eq. 03 with N_k counting the constant term;
 // N_s = 2 N_k cells including the target, so 2 N_k - 1 least-squares rows).
@@ -23,12 +29,16 @@ struct Dims {
   int rows = 0;    // all stencil rows: 3 * 11 small + nl
   int rows4 = 0;   // rows rounded up to a multiple of 4 (int4 loads)
   int J = 0;       // operator entries per cell: 3 * 5 * 11 + nu * nl
+  int lrow = 0;    // stored entries per large-stencil row: nu rounded up to even
+  int Jp = 0;      // stored entries per cell: 3 * 11 * 6 + nl * lrow (rows padded
+                   // to an even length so that pairs never straddle rows)
 };
 
 Dims dims_for(int order, int nq_req);
 
 constexpr int kSmallRows = 11;
 constexpr int kSmallCoef = 5;
+constexpr int kSmallStride = 6;  // stored entries per small-stencil row (one zero pad)
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -55,7 +65,7 @@ struct Mesh {
   // ---- packed device images, internal order, tile-major ----
   int n_pad = 0, n_tiles = 0;
   std::vector<int32_t> idx;     // [n_tiles][rows4][16][4] stencil members (internal)
-  std::vector<double> M;        // [n_tiles][J][16] operator entries, cells innermost
+  std::vector<double> M;        // [n_tiles][Jp/2][kTile][2] operator entries (pairs)
   std::vector<int32_t> nbinfo;  // [n_pad][4]: 3 neighbours + packed edge/side bits
   std::vector<double> geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area
   std::vector<int32_t> user_of; // [n_pad] user id (diagnostics)
@@ -64,13 +74,17 @@ struct Mesh {
   std::vector<int32_t> rev_ent; // i * rows4*4 + r, internal ids
 };
 
-// Entry j of the operator stream of one cell:
-//   small stencil k (0..2), row s, coefficient l: j = k*55 + s*5 + l
-//   large stencil row s, coefficient l:           j = 165 + s*nu + l
+// Stored entry of the operator stream of one cell (rows padded to even length):
+//   small stencil k (0..2), row s, coefficient l: j = k*66 + s*6 + l
+//   large stencil row s, coefficient l:           j = 198 + s*lrow + l
 // Stencil row order: rows 0..32 small stencils (11 each), then nl large rows.
+// Layout [tile][j/2][cell][2]: a lane reads both entries of a pair with one
+// 16-byte load.
+inline int entry_small(int k, int s, int l) { return k * kSmallRows * kSmallStride + s * kSmallStride + l; }
+inline int entry_large(const Dims& d, int s, int l) { return 3 * kSmallRows * kSmallStride + s * d.lrow + l; }
 inline int64_t packed_M_index(const Mesh& m, int internal, int j) {
   int t = internal / kTile, c = internal % kTile;
-  return ((int64_t)t * m.d.J + j) * kTile + c;
+  return (((int64_t)t * (m.d.Jp / 2) + (j >> 1)) * kTile + c) * 2 + (j & 1);
 }
 
 inline int64_t packed_idx_index(const Mesh& m, int internal, int row) {

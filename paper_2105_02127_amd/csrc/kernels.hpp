@@ -185,7 +185,7 @@ __device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, dou
 struct ReconArgs {
   const double* __restrict__ U;        // [n_cell][4]
   const int4* __restrict__ idx;        // [n_tiles][rows4][16] int4
-  const double* __restrict__ M;        // [n_tiles][J][16]
+  const double2* __restrict__ M;       // [n_tiles][JP/2][kTile] entry pairs
   double* __restrict__ fp;             // [3 nq][n_pad][4]
   uint16_t* flags;                     // out, or in when frozen
   const int32_t* __restrict__ user_of; // [n_pad]
@@ -236,11 +236,13 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// Least-squares phase over NR stencil rows starting at row R0 whose rows
-// carry NC operator entries each, starting at entry J0.  Row r gathers this
-// lane's variable g of member r, forms d = U_member - U_0 for all four
-// variables by quad broadcast, and adds M[l] d to acc[t][v] for the
-// coefficients l = g + 4t this lane owns.  Rows are visited in order, so
+// Least-squares phase over NR stencil rows starting at row R0; row s keeps
+// its operator entries at stored entries J0 + s*RS + l (RS even, entries
+// past the coefficient count are zero).  Each cell has LPC = 64 / kTile lanes
+// (g = 0..LPC-1); lane g gathers variable g % 4 of member r, forms
+// d = U_member - U_0 for all four variables by quad broadcast, and adds
+// M[l] d to acc[t][k][v] for the entry pairs p = g + LPC t it owns
+// (coefficients l = 2p + k), read with one 16-byte load per pair.  Rows are visited in order, so
 // every coefficient is summed over the rows in the same order as a plain
 // GEMV.
 //
@@ -251,31 +253,43 @@ __device__ __forceinline__ void static_for(F&& f) {
 // iterations (a rotating buffer would force a full wait every row; deeper
 // buffering or unrolling lets the compiler raise register use and lose
 // occupancy).
-template <int R0, int NR, int J0, int NC>
+// Pairs of stored entries per lane for a row of RS stored entries.
+template <int RS>
+constexpr int kSlots = (RS / 2 + kLanesPerCell - 1) / kLanesPerCell;
+
+template <int R0, int NR, int J0, int RS>
 __device__ __forceinline__ void split_rows(const double* __restrict__ U, const int* sidx, int c,
-                                           const double* __restrict__ mp, int g, double u0g,
-                                           double (&acc)[(NC + 3) / 4][4]) {
-  constexpr int NT = (NC + 3) / 4;
-  auto issue = [&](int s, double& x, double (&m)[NT]) {
+                                           const double2* __restrict__ mp, int g, double u0g,
+                                           double (&acc)[kSlots<RS>][2][4]) {
+  constexpr int NT = kSlots<RS>;
+  constexpr int LPC = kLanesPerCell;
+  constexpr int NPAIR = RS / 2;
+  const int v = g & 3;
+  auto issue = [&](int s, double& x, double2 (&m)[NT]) {
     const int r = R0 + s;
     const int id = sidx[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
-    x = U[(size_t)id * 4 + g];
-    const double* __restrict__ mr = mp + (size_t)(J0 + s * NC) * kTile;
+    x = U[(size_t)id * 4 + v];
+    const double2* __restrict__ mr = mp + (size_t)((J0 + s * RS) / 2) * kTile;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int l = g + 4 * t;
-      m[t] = (4 * t + 3 < NC || l < NC) ? mr[(size_t)l * kTile] : 0.0;
+      const int pr = g + LPC * t;
+      m[t] = (LPC * t + LPC - 1 < NPAIR || pr < NPAIR) ? mr[(size_t)pr * kTile]
+                                                        : make_double2(0.0, 0.0);
     }
   };
-  auto accumulate = [&](double xv, const double (&m)[NT]) {
+  auto accumulate = [&](double xv, const double2 (&m)[NT]) {
     const double x = xv - u0g;
     const double d[4] = {quad_bcast<0>(x), quad_bcast<1>(x), quad_bcast<2>(x), quad_bcast<3>(x)};
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[t][v] = fma(m[t], d[v], acc[t][v]);
+      for (int q = 0; q < 4; ++q) {
+        acc[t][0][q] = fma(m[t].x, d[q], acc[t][0][q]);
+        acc[t][1][q] = fma(m[t].y, d[q], acc[t][1][q]);
+      }
   };
-  double xa, xb, ma[NT], mb[NT];
+  double xa, xb;
+  double2 ma[NT], mb[NT];
   issue(0, xa, ma);
   int s = 0;
 #pragma unroll 1
@@ -288,12 +302,20 @@ __device__ __forceinline__ void split_rows(const double* __restrict__ U, const i
   if (s < NR) accumulate(xa, ma);
 }
 
-// Coefficient L of variable g, held by lane L%4 of the quad in slot L/4.
+// Coefficient L of variable v: pair L/2 is held by lane (L/2) % LPC of the
+// cell's lane group in slot (L/2) / LPC, component L % 2.
 template <int L, int NT>
-__device__ __forceinline__ double coef_of(const double (&acc)[NT][4], int g) {
-  constexpr int src = L & 3, t = L >> 2;
-  return pick4(quad_bcast<src>(acc[t][0]), quad_bcast<src>(acc[t][1]),
-               quad_bcast<src>(acc[t][2]), quad_bcast<src>(acc[t][3]), g);
+__device__ __forceinline__ double coef_of(const double (&acc)[NT][2][4], int v, int lane) {
+  constexpr int LPC = kLanesPerCell;
+  constexpr int src = (L / 2) % LPC, t = (L / 2) / LPC, k = L % 2;
+  if constexpr (LPC == 4) {
+    return pick4(quad_bcast<src>(acc[t][k][0]), quad_bcast<src>(acc[t][k][1]),
+                 quad_bcast<src>(acc[t][k][2]), quad_bcast<src>(acc[t][k][3]), v);
+  } else {
+    const int sl = (lane & ~(LPC - 1)) | src;
+    return pick4(__shfl(acc[t][k][0], sl), __shfl(acc[t][k][1], sl), __shfl(acc[t][k][2], sl),
+                 __shfl(acc[t][k][3], sl), v);
+  }
 }
 
 // Occupancy target of the reconstruction kernel (waves per SIMD); 0 leaves
@@ -324,27 +346,38 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
   __syncthreads();
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
   const int* sidx = reinterpret_cast<const int*>(sidx4[wave]);
-  const int c = lane >> 2, g = lane & 3;  // g: coefficient group, then variable
+  // g: coefficient group of the lane within its cell; v = g % 4: the
+  // variable it gathers and, in the selection phase, the variable it owns
+  // (with 8 lanes per cell, lanes 4..7 repeat 0..3 and do not write).
+  const int c = lane / kLanesPerCell, g = lane % kLanesPerCell, v = g & 3;
+  const bool writer = g < 4;
   const int cell = tile * kTile + c;
   const bool live = cell < a.n_cell;
-  const double u0 = a.U[(size_t)(live ? cell : 0) * 4 + g];
-  const double* __restrict__ mp = a.M + (size_t)tile * O::J * kTile + c;
+  const double u0 = a.U[(size_t)(live ? cell : 0) * 4 + v];
+  const double2* __restrict__ mp = a.M + (size_t)tile * (O::JP / 2) * kTile + c;
   const bool frozen = a.frozen != 0;
-  const unsigned nib_in = (frozen && live) ? ((a.flags[cell] >> (4 * g)) & 0xFu) : 8u;
+  const unsigned nib_in = (frozen && live) ? ((a.flags[cell] >> (4 * v)) & 0xFu) : 8u;
 
   // ---- small stencils (rows 0..32, entries 0..164), then step two of the
   //      selection, which needs only their indicators ----
   double as[3][5];
   {
-    double s0[2][4] = {}, s1[2][4] = {}, s2[2][4] = {};
-    split_rows<0, 11, 0, 5>(a.U, sidx, c, mp, g, u0, s0);
-    split_rows<11, 11, 55, 5>(a.U, sidx, c, mp, g, u0, s1);
-    split_rows<22, 11, 110, 5>(a.U, sidx, c, mp, g, u0, s2);
-    static_for<0, 5>([&](auto L) {
-      as[0][L] = coef_of<L, 2>(s0, g);
-      as[1][L] = coef_of<L, 2>(s1, g);
-      as[2][L] = coef_of<L, 2>(s2, g);
-    });
+    constexpr int NS = kSlots<O::SROW>;
+    {
+      double sk[NS][2][4] = {};
+      split_rows<0, 11, 0, O::SROW>(a.U, sidx, c, mp, g, u0, sk);
+      static_for<0, 5>([&](auto L) { as[0][L] = coef_of<L, NS>(sk, v, lane); });
+    }
+    {
+      double sk[NS][2][4] = {};
+      split_rows<11, 11, 11 * O::SROW, O::SROW>(a.U, sidx, c, mp, g, u0, sk);
+      static_for<0, 5>([&](auto L) { as[1][L] = coef_of<L, NS>(sk, v, lane); });
+    }
+    {
+      double sk[NS][2][4] = {};
+      split_rows<22, 11, 22 * O::SROW, O::SROW>(a.U, sidx, c, mp, g, u0, sk);
+      static_for<0, 5>([&](auto L) { as[2][L] = coef_of<L, NS>(sk, v, lane); });
+    }
   }
   unsigned nsm = nib_in & 7u;
   int ties_small = 0;
@@ -378,10 +411,10 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
   // ---- large stencil (rows 33.., entries 165..) ----
   double aK[NU];
   {
-    constexpr int NT = (NU + 3) / 4;
-    double sk[NT][4] = {};
-    split_rows<33, O::NL, 165, NU>(a.U, sidx, c, mp, g, u0, sk);
-    static_for<0, NU>([&](auto L) { aK[L] = coef_of<L, NT>(sk, g); });
+    constexpr int NT = kSlots<O::LROW>;
+    double sk[NT][2][4] = {};
+    split_rows<33, O::NL, 33 * O::SROW, O::LROW>(a.U, sidx, c, mp, g, u0, sk);
+    static_for<0, NU>([&](auto L) { aK[L] = coef_of<L, NT>(sk, v, lane); });
   }
   bool keepK = true;
   int ties = 0;
@@ -399,7 +432,7 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
 #pragma unroll
   for (int l = 0; l < NU; ++l) ab[l] = keepK ? aK[l] : (l < 5 ? asm_[l] : 0.0);
 
-  // ---- face Gauss points (variable g of this cell) ----
+  // ---- face Gauss points (variable v of this cell) ----
   double val[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
@@ -417,7 +450,7 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
     for (int q = 0; q < NP; ++q)
       fp_ok = fp_ok && physical(quad_bcast<0>(val[q]), quad_bcast<1>(val[q]),
                                 quad_bcast<2>(val[q]), quad_bcast<3>(val[q]), a.gamma);
-    if (live && g == 0 && !(avg_ok && fp_ok)) {
+    if (live && g == 0 && !(avg_ok && fp_ok)) {  // one lane per cell
       atomicAdd(&a.diag->nonphysical, 1ull);
       atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
     }
@@ -427,14 +460,14 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
       nib = 0u;
       if (live && g == 0) atomicAdd(&a.diag->fallbacks, 1ull);
     }
-    if (live && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
+    if (live && writer && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
   }
-  if (live) {
+  if (live && writer) {
 #pragma unroll
-    for (int q = 0; q < NP; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + g] = val[q];
+    for (int q = 0; q < NP; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + v] = val[q];
   }
   if (!frozen && a.flags) {
-    unsigned f = nib << (4 * g);
+    unsigned f = nib << (4 * v);
     f |= __shfl_xor(f, 1);
     f |= __shfl_xor(f, 2);
     if (live && g == 0) a.flags[cell] = (uint16_t)f;
@@ -648,7 +681,7 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
 struct AdjReconArgs {
   const double* __restrict__ fpbar;
   const uint16_t* __restrict__ flags;
-  const double* __restrict__ M;
+  const double2* __restrict__ M;
   double* __restrict__ dbar;   // [rows4*4][n_pad][4]
   double* __restrict__ own;    // [n_pad][4]
   int n_cell, n_tiles, n_pad;
@@ -662,9 +695,9 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   const int lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (tile >= a.n_tiles) return;
-  const int c = lane >> 2, v = lane & 3;
+  const int c = lane / kLanesPerCell, v = lane % kLanesPerCell;
   const int cell = tile * kTile + c;
-  if (cell >= a.n_cell) return;
+  if (cell >= a.n_cell || v >= 4) return;
   const unsigned nib = (a.flags[cell] >> (4 * v)) & 0xFu;
   double gsum = 0.0;
   double ab[NU];
@@ -677,7 +710,10 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
 #pragma unroll
     for (int l = 0; l < NU; ++l) ab[l] = fma(FaceBasis<O::R, NQ>::P.v[q][l], gq, ab[l]);
   }
-  const double* __restrict__ mp = a.M + (size_t)tile * O::J * kTile + c;
+  // stored entry j of this cell: component j%2 of pair j/2
+  const double* __restrict__ mp =
+      reinterpret_cast<const double*>(a.M + (size_t)tile * (O::JP / 2) * kTile + c);
+  auto entry = [&](int j) { return mp[(size_t)(j >> 1) * (2 * kTile) + (j & 1)]; };
   const bool keepK = nib & 8u;
   const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
   double dsum = 0.0;
@@ -690,8 +726,8 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
       double d = 0.0;
 #pragma unroll
       for (int l = 0; l < 5; ++l) {
-        const int j = k * 55 + s * 5 + l;
-        d = fma(mp[(size_t)j * kTile], ab[l], d);
+        const int j = k * 11 * O::SROW + s * O::SROW + l;
+        d = fma(entry(j), ab[l], d);
       }
       d *= wk;
       dsum += d;
@@ -704,8 +740,8 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
     double d = 0.0;
 #pragma unroll
     for (int l = 0; l < NU; ++l) {
-      const int j = 165 + s * NU + l;
-      d = fma(mp[(size_t)j * kTile], ab[l], d);
+      const int j = 33 * O::SROW + s * O::LROW + l;
+      d = fma(entry(j), ab[l], d);
     }
     d *= wK;
     dsum += d;

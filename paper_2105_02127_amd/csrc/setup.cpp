@@ -44,6 +44,8 @@ Dims dims_for(int order, int nq_req) {
   d.rows = 3 * kSmallRows + d.nl;
   d.rows4 = (d.rows + 3) / 4;
   d.J = 3 * kSmallCoef * kSmallRows + d.nu * d.nl;
+  d.lrow = d.nu + (d.nu & 1);
+  d.Jp = 3 * kSmallRows * kSmallStride + d.nl * d.lrow;
   return d;
 }
 
@@ -463,7 +465,7 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   m.n_pad = m.n_tiles * kTile;
   try {
     m.idx.assign((size_t)m.n_tiles * d.rows4 * kTile * 4, 0);
-    m.M.assign((size_t)m.n_tiles * d.J * kTile, 0.0);
+    m.M.assign((size_t)m.n_tiles * d.Jp * kTile, 0.0);
   } catch (...) {
     return fail(TENO_ENOMEM, "host allocation of packed operators failed");
   }
@@ -487,7 +489,6 @@ int mesh_setup(Mesh& m, const teno_params& p) {
       const Basis& B = big ? Bl : Bs;
       const int nrow = big ? d.nl : kSmallRows;
       const int row0 = big ? 3 * kSmallRows : k * kSmallRows;
-      const int j0 = big ? 3 * kSmallCoef * kSmallRows : k * kSmallCoef * kSmallRows;
       auto report = [&](int code, const std::string& msg) {
         std::lock_guard<std::mutex> g(mu);
         if (i < err_cell) {
@@ -520,7 +521,8 @@ int mesh_setup(Mesh& m, const teno_params& p) {
       for (int s = 0; s < nrow; ++s) {
         m.idx[packed_idx_index(m, t, row0 + s)] = m.inv[mem[s]];
         for (int l = 0; l < B.n; ++l)
-          m.M[packed_M_index(m, t, j0 + s * B.n + l)] = op[(size_t)l * nrow + s];
+          m.M[packed_M_index(m, t, big ? entry_large(d, s, l) : entry_small(k, s, l))] =
+              op[(size_t)l * nrow + s];
       }
     }
     std::lock_guard<std::mutex> g(mu);

@@ -132,7 +132,10 @@ struct OrderT {
   static constexpr int NQ = (P + 1) / 2;
   static constexpr int ROWS = 33 + NL;
   static constexpr int ROWS4 = (ROWS + 3) / 4;
-  static constexpr int J = 165 + NU * NL;
+  static constexpr int J = 165 + NU * NL;         // operator entries
+  static constexpr int LROW = NU + (NU & 1);       // stored large-row length
+  static constexpr int SROW = 6;                   // stored small-row length
+  static constexpr int JP = 3 * 11 * SROW + NL * LROW;  // stored entries
 };
 
 }  // namespace teno

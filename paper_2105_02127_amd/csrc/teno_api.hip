@@ -65,7 +65,7 @@ struct teno_solver {
   teno_params prm{};
   int n_cell = 0, n_pad = 0, n_tiles = 0;
   int4* idx = nullptr;
-  double* M = nullptr;
+  double2* M = nullptr;
   int4* nbinfo = nullptr;
   double* geo = nullptr;
   int32_t* user_of = nullptr;
@@ -366,9 +366,10 @@ int teno_mesh_lsq_operator(const teno_mesh* m, int32_t cell, int32_t k, double* 
   const int t = x.inv[cell];
   const bool big = k == 3;
   const int nrow = big ? x.d.nl : kSmallRows, nco = big ? x.d.nu : kSmallCoef;
-  const int j0 = big ? 3 * kSmallCoef * kSmallRows : k * kSmallCoef * kSmallRows;
   for (int l = 0; l < nco; ++l)
-    for (int s = 0; s < nrow; ++s) M[(size_t)l * nrow + s] = x.M[packed_M_index(x, t, j0 + s * nco + l)];
+    for (int s = 0; s < nrow; ++s)
+      M[(size_t)l * nrow + s] =
+          x.M[packed_M_index(x, t, big ? entry_large(x.d, s, l) : entry_small(k, s, l))];
   return nrow;
 }
 
@@ -401,7 +402,7 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
     if (rc == TENO_OK) rc = s->alloc(p, n);
   };
   A(s->idx, m.idx.size() / 4);
-  A(s->M, m.M.size());
+  A(s->M, m.M.size() / 2);
   A(s->nbinfo, np);
   A(s->geo, np * 10);
   A(s->user_of, np);
