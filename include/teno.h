@@ -39,6 +39,7 @@ typedef enum teno_status {
 
 typedef struct teno_mesh teno_mesh;
 typedef struct teno_solver teno_solver;
+typedef struct teno_batch teno_batch;
 
 /* Scheme parameters.  Defaults (teno_default_params) are the paper's fixed
  * built-in values: C_T = 1e-6 in both selection steps and eps = 1e-12 with
@@ -180,6 +181,41 @@ int teno_diagnostics(teno_solver* s, teno_diag* out, int32_t reset, void* stream
  * 2 dt, 3 adjoint), the summed milliseconds and launch counts; synchronises. */
 int teno_profile_enable(teno_solver* s, int32_t on);
 int teno_profile_read(teno_solver* s, double* ms, int64_t* launches, int32_t reset);
+
+/* ---- batch of independent meshes --------------------------------------- */
+
+/* Schedule of a batch (teno_batch_set_tuning). */
+typedef struct teno_batch_tuning {
+  int32_t order_mode;    /* 0: one reconstruction launch per stage for every
+                            order (dispatch per work item); 1: one launch per
+                            order present, each with that order's registers */
+  int32_t waves_per_cu;  /* persistent wavefronts per compute unit, 1..32     */
+  int32_t item_order;    /* 0: mesh order; 1: largest order first            */
+  int32_t use_graph;     /* 1: capture one step as a HIP graph and replay it  */
+} teno_batch_tuning;
+
+/* Groups solvers created on the same device (meshes of any size and order,
+ * each set up with its own parameters) so that one SSP-RK3 step of all of
+ * them runs as persistent launches over a shared work list: per stage one
+ * reconstruction launch (or one per order, see tuning) over (mesh, tile)
+ * items and one flux/update launch over (mesh, 64-cell) items.  The solvers
+ * must outlive the batch; their workspaces are reused. */
+int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out);
+
+int teno_batch_set_tuning(teno_batch* b, const teno_batch_tuning* t);
+int teno_batch_get_tuning(const teno_batch* b, teno_batch_tuning* t);
+
+/* dt_dev[m] = CFL step of mesh m from U[m] (device double[n]); two launches. */
+int teno_batch_max_dt(teno_batch* b, double* const* U, double cfl, double* dt_dev, void* stream);
+
+/* One SSP-RK3 step of every mesh, in place on U[m] (device state of mesh m,
+ * internal order), with step dt_dev[m].  With use_graph the first call (and
+ * any call with different pointers or tuning) captures the step as a HIP
+ * graph; later calls replay it.  U (host array of n device pointers) and
+ * dt_dev are read at capture time. */
+int teno_batch_rk_step(teno_batch* b, double* const* U, const double* dt_dev, void* stream);
+
+void teno_batch_destroy(teno_batch* b);
 
 #ifdef __cplusplus
 }

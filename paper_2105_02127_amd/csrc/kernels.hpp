@@ -329,23 +329,32 @@ __device__ __forceinline__ double coef_of(const double (&acc)[NT][2][4], int v, 
 #define TENO_RECON_ATTR
 #endif
 
+// LDS ordering between the lanes of one wavefront (staged indices).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Largest per-wavefront LDS staging area (order 6).
+constexpr int kMaxStage = OrderT<6>::ROWS4 * kTile;
+
+// Reconstruction of one tile of kTile cells by one wavefront; `stage` is
+// this wavefront's LDS area (at least ROWS4 * kTile int4).
 template <int P, int NQ>
-__global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a) {
+__device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, int lane,
+                                                 int4* stage) {
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   // stage this tile's stencil member indices in LDS ([row4][cell][4] ints)
-  __shared__ int4 sidx4[4][O::ROWS4 * kTile];
-  if (tile < a.n_tiles) {
+  wave_lds_sync();  // earlier readers of `stage` are done
+  {
     const int4* __restrict__ src = a.idx + (size_t)tile * O::ROWS4 * kTile;
-    for (int i = lane; i < O::ROWS4 * kTile; i += 64) sidx4[wave][i] = src[i];
+    for (int i = lane; i < O::ROWS4 * kTile; i += 64) stage[i] = src[i];
   }
-  __syncthreads();
-  if (tile >= a.n_tiles) return;  // whole wavefront leaves together
-  const int* sidx = reinterpret_cast<const int*>(sidx4[wave]);
+  wave_lds_sync();
+  const int* sidx = reinterpret_cast<const int*>(stage);
   // g: coefficient group of the lane within its cell; v = g % 4: the
   // variable it gathers and, in the selection phase, the variable it owns
   // (with 8 lanes per cell, lanes 4..7 repeat 0..3 and do not write).
@@ -474,6 +483,15 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
   }
 }
 
+template <int P, int NQ>
+__global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a) {
+  __shared__ int4 stage[4][OrderT<P>::ROWS4 * kTile];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= a.n_tiles) return;  // whole wavefront leaves together
+  reconstruct_tile<P, NQ>(a, tile, lane, stage[wave]);
+}
+
 // ---------------------------------------------------------------------------
 // flux, residual, Runge-Kutta stage
 // ---------------------------------------------------------------------------
@@ -491,9 +509,7 @@ struct FluxArgs {
 };
 
 template <int NQ, bool RK>
-__global__ __launch_bounds__(256) void k_flux_update(FluxArgs a) {
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (t >= a.n_cell) return;
+__device__ __forceinline__ void flux_cell(const FluxArgs& a, int t) {
   const int4 nb = a.nbinfo[t];
   const double* g = a.geo + (size_t)t * 10;
   const double2* fp2 = reinterpret_cast<const double2*>(a.fp);
@@ -544,6 +560,13 @@ __global__ __launch_bounds__(256) void k_flux_update(FluxArgs a) {
   }
 }
 
+template <int NQ, bool RK>
+__global__ __launch_bounds__(256) void k_flux_update(FluxArgs a) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (t >= a.n_cell) return;
+  flux_cell<NQ, RK>(a, t);
+}
+
 // ---------------------------------------------------------------------------
 // time step
 // ---------------------------------------------------------------------------
@@ -561,26 +584,29 @@ __device__ __forceinline__ double block_min(double x, double* sh) {
   return sh[0];
 }
 
+// |V_i| / sum_j |A_ij| (|u_i . n_ij| + c_i) from the cell average of cell t.
+__device__ __forceinline__ double cell_dt_limit(const double* __restrict__ U,
+                                                const double* __restrict__ geo, int t, double g) {
+  const double* u = U + (size_t)t * 4;
+  const double* gg = geo + (size_t)t * 10;
+  const double vx = u[1] / u[0], vy = u[2] / u[0];
+  const double p = (g - 1.0) * (u[3] - 0.5 * u[0] * (vx * vx + vy * vy));
+  const double c = sqrt(g * p / u[0]);
+  double den = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const double un = vx * gg[3 * e] + vy * gg[3 * e + 1];
+    den = den + gg[3 * e + 2] * (fabs(un) + c);
+  }
+  return gg[9] / den;
+}
+
 __global__ __launch_bounds__(256) void k_dt_partial(const double* __restrict__ U,
                                                     const double* __restrict__ geo, int n,
                                                     double g, double* __restrict__ partial) {
   __shared__ double sh[4];
   const int t = blockIdx.x * 256 + threadIdx.x;
-  double lim = INFINITY;
-  if (t < n) {
-    const double* u = U + (size_t)t * 4;
-    const double* gg = geo + (size_t)t * 10;
-    const double vx = u[1] / u[0], vy = u[2] / u[0];
-    const double p = (g - 1.0) * (u[3] - 0.5 * u[0] * (vx * vx + vy * vy));
-    const double c = sqrt(g * p / u[0]);
-    double den = 0.0;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const double un = vx * gg[3 * e] + vy * gg[3 * e + 1];
-      den = den + gg[3 * e + 2] * (fabs(un) + c);
-    }
-    lim = gg[9] / den;
-  }
+  const double lim = t < n ? cell_dt_limit(U, geo, t, g) : INFINITY;
   const double m = block_min(lim, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
@@ -793,6 +819,107 @@ __global__ __launch_bounds__(256) void k_lincomb(double* out, double a1, const d
   if (x2) s = s + a2 * x2[i];
   if (x3) s = s + a3 * x3[i];
   out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent meshes
+// ---------------------------------------------------------------------------
+// One mesh of a batch: the arguments of its three RK stages.
+struct BatchMeshDev {
+  ReconArgs r[3];          // reconstruction input of stage k
+  FluxArgs f[3];           // flux, gather and update of stage k
+  const double* U;         // cell averages at the start of the step
+  const double* geo;
+  double* dt;              // this mesh's step (device scalar)
+  double gamma;
+  int pq;                  // order * 10 + face points
+  int n_cell;
+};
+
+// Runs reconstruct_tile for pq (any supported pair when PQ == 0, otherwise
+// only PQ, so a per-order launch keeps that order's register budget).
+template <int PQ>
+__device__ __forceinline__ void batch_tile(int pq, const ReconArgs& a, int tile, int lane,
+                                           int4* stage) {
+  if (PQ != 0) pq = PQ;
+  switch (pq) {
+    case 32: reconstruct_tile<3, 2>(a, tile, lane, stage); break;
+    case 42: reconstruct_tile<4, 2>(a, tile, lane, stage); break;
+    case 53: reconstruct_tile<5, 3>(a, tile, lane, stage); break;
+    case 63: reconstruct_tile<6, 3>(a, tile, lane, stage); break;
+    case 33: if (PQ == 0 || PQ == 33) reconstruct_tile<3, 3>(a, tile, lane, stage); break;
+    case 43: if (PQ == 0 || PQ == 43) reconstruct_tile<4, 3>(a, tile, lane, stage); break;
+    case 52: if (PQ == 0 || PQ == 52) reconstruct_tile<5, 2>(a, tile, lane, stage); break;
+    case 62: if (PQ == 0 || PQ == 62) reconstruct_tile<6, 2>(a, tile, lane, stage); break;
+    default: break;
+  }
+}
+
+// Persistent reconstruction over a work list of (mesh, tile) items: each
+// wavefront takes the contiguous, cost-balanced item range
+// [wave_start[w], wave_start[w+1]) and leaves when it is done.
+template <int PQ>
+__global__ __launch_bounds__(256) void k_batch_reconstruct(const BatchMeshDev* __restrict__ meshes,
+                                                           const int2* __restrict__ items,
+                                                           const int* __restrict__ wave_start,
+                                                           int n_waves, int stage_k) {
+  __shared__ int4 stage[4][kMaxStage];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (w >= n_waves) return;
+  const int i0 = wave_start[w], i1 = wave_start[w + 1];
+  for (int i = i0; i < i1; ++i) {
+    const int2 it = items[i];
+    const int m = __builtin_amdgcn_readfirstlane(it.x);
+    const int tile = __builtin_amdgcn_readfirstlane(it.y);
+    const BatchMeshDev& d = meshes[m];
+    batch_tile<PQ>(d.pq, d.r[stage_k], tile, lane, stage[wave]);
+  }
+}
+
+// Persistent flux + gather + stage update over (mesh, 64-cell chunk) items.
+__global__ __launch_bounds__(256) void k_batch_flux(const BatchMeshDev* __restrict__ meshes,
+                                                    const int2* __restrict__ items,
+                                                    const int* __restrict__ wave_start,
+                                                    int n_waves, int stage_k) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (w >= n_waves) return;
+  const int i0 = wave_start[w], i1 = wave_start[w + 1];
+  for (int i = i0; i < i1; ++i) {
+    const int2 it = items[i];
+    const int m = __builtin_amdgcn_readfirstlane(it.x);
+    const BatchMeshDev& d = meshes[m];
+    const int t = it.y * 64 + lane;
+    if (t >= d.n_cell) continue;
+    if (d.pq % 10 == 2) flux_cell<2, true>(d.f[stage_k], t);
+    else flux_cell<3, true>(d.f[stage_k], t);
+  }
+}
+
+// Per-mesh dt: one block per (mesh, 256-cell block) item, then one block per mesh.
+__global__ __launch_bounds__(256) void k_batch_dt_partial(const BatchMeshDev* __restrict__ meshes,
+                                                          const int2* __restrict__ items,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int2 it = items[blockIdx.x];
+  const BatchMeshDev& d = meshes[it.x];
+  const int t = it.y * 256 + threadIdx.x;
+  const double lim = t < d.n_cell ? cell_dt_limit(d.U, d.geo, t, d.gamma) : INFINITY;
+  const double m = block_min(lim, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_batch_dt_final(const BatchMeshDev* __restrict__ meshes,
+                                                        const int* __restrict__ item_start,
+                                                        const double* __restrict__ partial,
+                                                        double cfl) {
+  __shared__ double sh[4];
+  double x = INFINITY;
+  for (int i = item_start[blockIdx.x] + threadIdx.x; i < item_start[blockIdx.x + 1]; i += 256)
+    x = fmin(x, partial[i]);
+  const double m = block_min(x, sh);
+  if (threadIdx.x == 0) *meshes[blockIdx.x].dt = cfl * m;
 }
 
 __global__ void k_diag_reset(DevDiag* d) {

@@ -59,6 +59,11 @@ int hip_fail(hipError_t e, const char* what) {
 
 }  // namespace
 
+// SSP-RK3 stage k: U^(k+1) = A[k] U^n + B[k] U^(k) + C[k] dt R(U^(k)).
+static const double kStageA[3] = {1.0, 0.75, 1.0 / 3.0};
+static const double kStageB[3] = {0.0, 0.25, 2.0 / 3.0};
+static const double kStageC[3] = {1.0, 0.25, 2.0 / 3.0};
+
 struct teno_solver {
   int device = 0;
   Dims d;
@@ -504,9 +509,6 @@ int teno_max_dt(teno_solver* s, const double* U, double cfl, double* dt_dev, voi
   return launch_dt(s, U, cfl, dt_dev, (hipStream_t)stream);
 }
 
-static const double kStageA[3] = {1.0, 0.75, 1.0 / 3.0};
-static const double kStageB[3] = {0.0, 0.25, 2.0 / 3.0};
-static const double kStageC[3] = {1.0, 0.25, 2.0 / 3.0};
 
 static int stage_impl(teno_solver* s, int k, const double* Un, const double* Uk, double* Uk1,
                       const double* dt, uint16_t* flags, bool frozen, hipStream_t st) {
@@ -637,6 +639,383 @@ int teno_profile_read(teno_solver* s, double* ms, int64_t* launches, int32_t res
     }
   }
   return TENO_OK;
+}
+
+// ===========================================================================
+// batches
+// ===========================================================================
+}  // extern "C"
+
+struct teno_batch {
+  int device = 0;
+  int n = 0;
+  int n_cu = 256;
+  std::vector<teno_solver*> sv;
+  teno_batch_tuning tune{0, 8, 1, 1};
+  // device data
+  BatchMeshDev* meshes = nullptr;
+  int2* items_r = nullptr;     // reconstruction items, all orders
+  int* start_r = nullptr;      // wave starts per launch, concatenated
+  int2* items_f = nullptr;
+  int* start_f = nullptr;
+  int2* items_dt = nullptr;
+  int* start_dt = nullptr;     // per mesh
+  double* partial = nullptr;
+  // launch plan: per reconstruction launch (pq, item offset, wave offset, waves)
+  struct RLaunch {
+    int pq, item0, wave0, n_waves;
+  };
+  std::vector<RLaunch> rplan;
+  int n_waves_f = 0, n_items_dt = 0;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<double*> graph_U;
+  const double* graph_dt = nullptr;
+  hipStream_t graph_stream = nullptr;
+  std::vector<void*> allocs;
+
+  template <class T>
+  int alloc(T*& p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 256));
+    if (e != hipSuccess) return fail(TENO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    allocs.push_back(q);
+    p = (T*)q;
+    return TENO_OK;
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_U.clear();
+  }
+  void free_plan() {
+    for (void* q : allocs) (void)hipFree(q);
+    allocs.clear();
+    meshes = nullptr;
+  }
+  ~teno_batch() {
+    drop_graph();
+    free_plan();
+  }
+};
+
+namespace {
+
+// Splits items [0, n) with costs into `waves` contiguous ranges of nearly
+// equal total cost; writes waves+1 starts.
+void balanced_starts(const std::vector<double>& cost, int waves, std::vector<int>& starts) {
+  const int n = (int)cost.size();
+  double total = 0.0;
+  for (double c : cost) total += c;
+  starts.assign(waves + 1, n);
+  starts[0] = 0;
+  double acc = 0.0;
+  int w = 1;
+  for (int i = 0; i < n && w < waves; ++i) {
+    acc += cost[i];
+    while (w < waves && acc >= total * w / waves) starts[w++] = i + 1;
+  }
+  for (; w < waves; ++w) starts[w] = n;
+  starts[waves] = n;
+}
+
+int batch_plan(teno_batch* b) {
+  b->drop_graph();
+  b->free_plan();
+  const int n = b->n;
+  const teno_batch_tuning& T = b->tune;
+  const int waves = std::max(1, T.waves_per_cu) * b->n_cu;
+  // mesh order for the work list
+  std::vector<int> morder(n);
+  for (int m = 0; m < n; ++m) morder[m] = m;
+  if (T.item_order == 1)
+    std::stable_sort(morder.begin(), morder.end(), [&](int x, int y) {
+      return b->sv[x]->d.Jp > b->sv[y]->d.Jp;
+    });
+  // reconstruction items, grouped per launch
+  std::vector<int2> items;
+  std::vector<int> starts_all;
+  b->rplan.clear();
+  std::vector<int> pqs;
+  if (T.order_mode == 1) {
+    for (int m : morder) {
+      int pq = b->sv[m]->d.order * 10 + b->sv[m]->d.nq;
+      if (std::find(pqs.begin(), pqs.end(), pq) == pqs.end()) pqs.push_back(pq);
+    }
+  } else {
+    pqs.push_back(0);
+  }
+  for (int pq : pqs) {
+    std::vector<double> cost;
+    const int item0 = (int)items.size();
+    for (int m : morder) {
+      const teno_solver* s = b->sv[m];
+      const int mpq = s->d.order * 10 + s->d.nq;
+      if (pq != 0 && mpq != pq) continue;
+      for (int t = 0; t < s->n_tiles; ++t) {
+        items.push_back(make_int2(m, t));
+        cost.push_back((double)s->d.Jp + 4.0 * s->d.rows4 * 4);
+      }
+    }
+    std::vector<int> st;
+    balanced_starts(cost, waves, st);
+    for (int& x : st) x += item0;
+    b->rplan.push_back({pq, item0, (int)starts_all.size(), waves});
+    starts_all.insert(starts_all.end(), st.begin(), st.end());
+  }
+  // flux items (64-cell chunks) and dt items (256-cell blocks)
+  std::vector<int2> fitems, ditems;
+  std::vector<double> fcost;
+  std::vector<int> dstart(n + 1, 0);
+  for (int m : morder) {
+    const teno_solver* s = b->sv[m];
+    for (int u = 0; u < (s->n_cell + 63) / 64; ++u) {
+      fitems.push_back(make_int2(m, u));
+      fcost.push_back((double)s->d.nq);
+    }
+  }
+  for (int m = 0; m < n; ++m) {
+    dstart[m] = (int)ditems.size();
+    for (int u = 0; u < (b->sv[m]->n_cell + 255) / 256; ++u) ditems.push_back(make_int2(m, u));
+  }
+  dstart[n] = (int)ditems.size();
+  std::vector<int> fstart;
+  balanced_starts(fcost, waves, fstart);
+  b->n_waves_f = waves;
+  b->n_items_dt = (int)ditems.size();
+  int rc = TENO_OK;
+  auto A = [&](auto& p, size_t c) {
+    if (rc == TENO_OK) rc = b->alloc(p, c);
+  };
+  A(b->meshes, (size_t)n);
+  A(b->items_r, items.size());
+  A(b->start_r, starts_all.size());
+  A(b->items_f, fitems.size());
+  A(b->start_f, fstart.size());
+  A(b->items_dt, ditems.size());
+  A(b->start_dt, dstart.size());
+  A(b->partial, ditems.size());
+  if (rc) return rc;
+  struct Up {
+    void* d;
+    const void* h;
+    size_t bytes;
+  } ups[] = {{b->items_r, items.data(), items.size() * sizeof(int2)},
+             {b->start_r, starts_all.data(), starts_all.size() * sizeof(int)},
+             {b->items_f, fitems.data(), fitems.size() * sizeof(int2)},
+             {b->start_f, fstart.data(), fstart.size() * sizeof(int)},
+             {b->items_dt, ditems.data(), ditems.size() * sizeof(int2)},
+             {b->start_dt, dstart.data(), dstart.size() * sizeof(int)}};
+  for (auto& u : ups) {
+    hipError_t e = hipMemcpy(u.d, u.h, u.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+  }
+  return TENO_OK;
+}
+
+// Writes the per-mesh descriptors for state pointers U[m] and steps dt[m].
+int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStream_t st) {
+  std::vector<BatchMeshDev> h(b->n);
+  for (int m = 0; m < b->n; ++m) {
+    teno_solver* s = b->sv[m];
+    BatchMeshDev& d = h[m];
+    std::memset(&d, 0, sizeof(d));
+    const double* in[3] = {U[m], s->W1, s->W2};
+    double* out[3] = {s->W1, s->W2, U[m]};
+    for (int k = 0; k < 3; ++k) {
+      ReconArgs& a = d.r[k];
+      a.U = in[k];
+      a.idx = s->idx;
+      a.M = s->M;
+      a.fp = s->fp;
+      a.flags = nullptr;
+      a.user_of = s->user_of;
+      a.diag = s->diag;
+      a.n_cell = s->n_cell;
+      a.n_tiles = s->n_tiles;
+      a.n_pad = s->n_pad;
+      a.frozen = 0;
+      a.variant = s->prm.variant;
+      a.fallback = s->prm.fallback;
+      a.power = s->prm.power;
+      a.ct = s->prm.ct;
+      a.eps = s->prm.eps;
+      a.gamma = s->prm.gamma;
+      a.tie_rel = s->prm.tie_rel;
+      FluxArgs& f = d.f[k];
+      f.fp = s->fp;
+      f.nbinfo = s->nbinfo;
+      f.geo = s->geo;
+      f.Un = U[m];
+      f.Uk = in[k];
+      f.out = out[k];
+      f.dt = dt ? dt + m : nullptr;
+      f.ca = kStageA[k];
+      f.cb = kStageB[k];
+      f.cc = kStageC[k];
+      f.gamma = s->prm.gamma;
+      f.n_cell = s->n_cell;
+      f.n_pad = s->n_pad;
+    }
+    d.U = U[m];
+    d.geo = s->geo;
+    d.dt = dt ? const_cast<double*>(dt) + m : nullptr;
+    d.gamma = s->prm.gamma;
+    d.pq = s->d.order * 10 + s->d.nq;
+    d.n_cell = s->n_cell;
+  }
+  hipError_t e = hipMemcpyAsync(b->meshes, h.data(), h.size() * sizeof(BatchMeshDev),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+  return TENO_OK;
+}
+
+void batch_launch_recon(teno_batch* b, int k, hipStream_t st) {
+  for (const auto& L : b->rplan) {
+    const int blocks = (L.n_waves + 3) / 4;
+    const int* ws = b->start_r + L.wave0;
+    switch (L.pq) {
+#define TENO_BATCH_CASE(PQ)                                                                  \
+  case PQ:                                                                                   \
+    hipLaunchKernelGGL((k_batch_reconstruct<PQ>), dim3(blocks), dim3(256), 0, st, b->meshes, \
+                       b->items_r, ws, L.n_waves, k);                                        \
+    break;
+      TENO_BATCH_CASE(0)
+      TENO_BATCH_CASE(32)
+      TENO_BATCH_CASE(33)
+      TENO_BATCH_CASE(42)
+      TENO_BATCH_CASE(43)
+      TENO_BATCH_CASE(52)
+      TENO_BATCH_CASE(53)
+      TENO_BATCH_CASE(62)
+      TENO_BATCH_CASE(63)
+#undef TENO_BATCH_CASE
+      default: break;
+    }
+  }
+}
+
+void batch_launch_step(teno_batch* b, hipStream_t st) {
+  const int fblocks = (b->n_waves_f + 3) / 4;
+  for (int k = 0; k < 3; ++k) {
+    batch_launch_recon(b, k, st);
+    hipLaunchKernelGGL(k_batch_flux, dim3(fblocks), dim3(256), 0, st, b->meshes, b->items_f,
+                       b->start_f, b->n_waves_f, k);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out) {
+  if (!solvers || !out || n <= 0) return fail(TENO_EARG, "empty batch");
+  *out = nullptr;
+  for (int m = 0; m < n; ++m) {
+    if (!solvers[m]) return fail(TENO_EARG, "null solver in batch");
+    if (solvers[m]->device != solvers[0]->device) return fail(TENO_EARG, "batch solvers must share a device");
+    for (int k = 0; k < m; ++k)
+      if (solvers[k] == solvers[m]) return fail(TENO_EARG, "a solver appears twice in the batch");
+  }
+  DeviceScope ds(solvers[0]->device);
+  teno_batch* b = new (std::nothrow) teno_batch();
+  if (!b) return fail(TENO_ENOMEM, "host allocation failed");
+  b->device = solvers[0]->device;
+  b->n = n;
+  b->sv.assign(solvers, solvers + n);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess &&
+      cus > 0)
+    b->n_cu = cus;
+  int rc = batch_plan(b);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return TENO_OK;
+}
+
+int teno_batch_set_tuning(teno_batch* b, const teno_batch_tuning* t) {
+  if (!b || !t) return fail(TENO_EARG, "null argument");
+  if (t->order_mode < 0 || t->order_mode > 1 || t->item_order < 0 || t->item_order > 1 ||
+      t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->use_graph < 0 || t->use_graph > 1)
+    return fail(TENO_EARG, "tuning out of range");
+  DeviceScope ds(b->device);
+  b->tune = *t;
+  return batch_plan(b);
+}
+
+int teno_batch_get_tuning(const teno_batch* b, teno_batch_tuning* t) {
+  if (!b || !t) return fail(TENO_EARG, "null argument");
+  *t = b->tune;
+  return TENO_OK;
+}
+
+int teno_batch_max_dt(teno_batch* b, double* const* U, double cfl, double* dt_dev, void* stream) {
+  if (!b || !U || !dt_dev) return fail(TENO_EARG, "null argument");
+  if (!(cfl > 0.0)) return fail(TENO_EARG, "cfl must be positive");
+  for (int m = 0; m < b->n; ++m)
+    if (!U[m]) return fail(TENO_EARG, "null state pointer");
+  DeviceScope ds(b->device);
+  hipStream_t st = (hipStream_t)stream;
+  b->drop_graph();  // descriptors are rewritten below
+  int rc = batch_descriptors(b, U, dt_dev, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_batch_dt_partial, dim3(b->n_items_dt), dim3(256), 0, st, b->meshes,
+                     b->items_dt, b->partial);
+  hipLaunchKernelGGL(k_batch_dt_final, dim3(b->n), dim3(256), 0, st, b->meshes, b->start_dt,
+                     b->partial, cfl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "batch dt launch");
+  return TENO_OK;
+}
+
+int teno_batch_rk_step(teno_batch* b, double* const* U, const double* dt_dev, void* stream) {
+  if (!b || !U || !dt_dev) return fail(TENO_EARG, "null argument");
+  for (int m = 0; m < b->n; ++m)
+    if (!U[m]) return fail(TENO_EARG, "null state pointer");
+  DeviceScope ds(b->device);
+  hipStream_t st = (hipStream_t)stream;
+  bool same = b->exec && b->graph_dt == dt_dev && b->graph_stream == st &&
+              (int)b->graph_U.size() == b->n && std::equal(U, U + b->n, b->graph_U.begin());
+  if (!same) {
+    b->drop_graph();
+    int rc = batch_descriptors(b, U, dt_dev, st);
+    if (rc) return rc;
+    if (b->tune.use_graph) {
+      if (st == nullptr) return fail(TENO_EARG, "graph capture needs a non-default stream");
+      hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      batch_launch_step(b, st);
+      e = hipStreamEndCapture(st, &b->graph);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      b->graph_U.assign(U, U + b->n);
+      b->graph_dt = dt_dev;
+      b->graph_stream = st;
+    }
+  }
+  if (b->tune.use_graph) {
+    hipError_t e = hipGraphLaunch(b->exec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  } else {
+    batch_launch_step(b, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+  }
+  return TENO_OK;
+}
+
+void teno_batch_destroy(teno_batch* b) {
+  if (!b) return;
+  DeviceScope ds(b->device);
+  delete b;
 }
 
 }  // extern "C"

@@ -33,6 +33,11 @@ class Info(C.Structure):
                 ("min_rcond", C.c_double)]
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("order_mode", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("item_order", C.c_int32), ("use_graph", C.c_int32)]
+
+
 class Diag(C.Structure):
     _fields_ = [("nonphysical", C.c_int64), ("first_bad_cell", C.c_int64),
                 ("near_ties", C.c_int64), ("fallbacks", C.c_int64)]
@@ -63,6 +68,12 @@ SIGNATURES = {
     "teno_diagnostics": (C.c_int, [_vp, C.POINTER(Diag), _i32, _vp]),
     "teno_profile_enable": (C.c_int, [_vp, _i32]),
     "teno_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64), _i32]),
+    "teno_batch_create": (C.c_int, [C.POINTER(_vp), _i32, C.POINTER(_vp)]),
+    "teno_batch_set_tuning": (C.c_int, [_vp, C.POINTER(BatchTuning)]),
+    "teno_batch_get_tuning": (C.c_int, [_vp, C.POINTER(BatchTuning)]),
+    "teno_batch_max_dt": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, _vp, _vp]),
+    "teno_batch_rk_step": (C.c_int, [_vp, C.POINTER(_vp), _vp, _vp]),
+    "teno_batch_destroy": (None, [_vp]),
 }
 
 KERNEL_KINDS = ("reconstruct", "flux_update", "dt", "adjoint")
