@@ -121,6 +121,63 @@ def adjoint_timing(torch, teno, inputs, steps=200, checkpoint_every=20):
             "note": "backward includes recomputing each 20-step segment from its checkpoint"}
 
 
+def batch_timing(torch, teno, inputs, steps=10):
+    """Batched workload: 64 seeded jittered periodic meshes, N ~ U{32..316},
+    order ~ U{3..6}, random-line states; one step = per-mesh dt + one
+    SSP-RK3 step of every mesh.  Autotuned batched schedule against the same
+    meshes stepped one solver at a time."""
+    from paper_2105_02127_amd.batch import Batch, autotune
+    specs = inputs.batch_specs()
+    solvers, U0 = [], []
+    t0 = time.perf_counter()
+    for n, p, seed in specs:
+        m = inputs.jittered_periodic_mesh(n, seed)
+        lm = teno.Mesh(m.xy, m.tri).setup(order=p, fallback=1)
+        solvers.append(teno.Solver(lm))
+        U0.append(torch.as_tensor(inputs.random_lines(m)[lm.perm], device="cuda"))
+    t_setup = time.perf_counter() - t0
+    cells = sum(s.n_cell for s in solvers)
+    by_order = {}
+    for s in solvers:
+        by_order[s.order] = by_order.get(s.order, 0) + s.n_cell
+    b = Batch(solvers)
+    dt = b.max_dt(U0, 0.4)
+    best, timings = autotune(b, U0, dt, steps=3)
+    U = [u.clone() for u in U0]
+    for _ in range(2):
+        b.max_dt(U, 0.4, dt)
+        b.rk_step(U, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.max_dt(U, 0.4, dt)
+        b.rk_step(U, dt)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # the same meshes, one solver at a time
+    U = [u.clone() for u in U0]
+    dts = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in solvers]
+    for _ in range(2):
+        for s, u, d in zip(solvers, U, dts):
+            s.max_dt(u, 0.4, d)
+            s.rk_step(u, d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s, u, d in zip(solvers, U, dts):
+            s.max_dt(u, 0.4, d)
+            s.rk_step(u, d)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    return {"workload": "64 meshes, N~U{32..316}, order~U{3..6}, random lines", "meshes": len(solvers),
+            "n_cell": cells, "cells_by_order": by_order, "steps": steps,
+            "value": cells * 3 * steps / t_batch, "unit": "cell-updates/s",
+            "ms_per_step": t_batch * 1e3 / steps,
+            "single_mesh_sequential_value": cells * 3 * steps / t_seq,
+            "batched_over_sequential": t_seq / t_batch,
+            "tuning": best, "setup_s": t_setup}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +189,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -227,6 +285,8 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, teno, inputs)
+    if not args.no_batch:
+        out["batched"] = batch_timing(torch, teno, inputs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps)
     print(json.dumps(out), flush=True)
