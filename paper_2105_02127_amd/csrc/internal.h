@@ -29,16 +29,14 @@ struct Dims {
   int rows = 0;    // all stencil rows: 3 * 11 small + nl
   int rows4 = 0;   // rows rounded up to a multiple of 4 (int4 loads)
   int J = 0;       // operator entries per cell: 3 * 5 * 11 + nu * nl
-  int lrow = 0;    // stored entries per large-stencil row: nu rounded up to even
-  int Jp = 0;      // stored entries per cell: 3 * 11 * 6 + nl * lrow (rows padded
-                   // to an even length so that pairs never straddle rows)
+  int lblk = 0;    // stored entries of the large stencil (see block_entries)
+  int Jp = 0;      // stored entries per cell: 3 * kSmallBlock + lblk
 };
 
 Dims dims_for(int order, int nq_req);
 
 constexpr int kSmallRows = 11;
 constexpr int kSmallCoef = 5;
-constexpr int kSmallStride = 6;  // stored entries per small-stencil row (one zero pad)
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -74,14 +72,26 @@ struct Mesh {
   std::vector<int32_t> rev_ent; // i * rows4*4 + r, internal ids
 };
 
-// Stored entry of the operator stream of one cell (rows padded to even length):
-//   small stencil k (0..2), row s, coefficient l: j = k*66 + s*6 + l
-//   large stencil row s, coefficient l:           j = 198 + s*lrow + l
-// Stencil row order: rows 0..32 small stencils (11 each), then nl large rows.
-// Layout [tile][j/2][cell][2]: a lane reads both entries of a pair with one
-// 16-byte load.
-inline int entry_small(int k, int s, int l) { return k * kSmallRows * kSmallStride + s * kSmallStride + l; }
-inline int entry_large(const Dims& d, int s, int l) { return 3 * kSmallRows * kSmallStride + s * d.lrow + l; }
+// Stencil row order of a cell: rows 0..32 hold the three small stencils
+// (row s of small stencil k is row 11k + s), then the nl large-stencil rows.
+constexpr int small_row(int k, int s) { return kSmallRows * k + s; }
+constexpr int large_row(int s) { return 3 * kSmallRows + s; }
+
+// Stored operator entries of one stencil (M^T, nrow rows of L coefficients):
+// rows back to back, each padded with a zero to an even length so that a
+// 16-byte pair never straddles two rows.  (Packing the entries densely
+// needs more lanes or registers per row in the kernel and measured slower
+// than streaming the padding.)
+constexpr int stored_row(int L) { return L + (L & 1); }
+constexpr int block_entries(int nrow, int L) { return nrow * stored_row(L); }
+constexpr int entry_in_block(int L, int s, int l) { return s * stored_row(L) + l; }
+constexpr int kSmallBlock = block_entries(kSmallRows, kSmallCoef);  // 66
+
+// Stored entry of the operator stream of one cell: the three small stencils'
+// blocks, then the large stencil's.  Layout [tile][j/2][cell][2]: a lane
+// reads both entries of a pair with one 16-byte load.
+inline int entry_small(int k, int s, int l) { return kSmallBlock * k + entry_in_block(kSmallCoef, s, l); }
+inline int entry_large(const Dims& d, int s, int l) { return 3 * kSmallBlock + entry_in_block(d.nu, s, l); }
 inline int64_t packed_M_index(const Mesh& m, int internal, int j) {
   int t = internal / kTile, c = internal % kTile;
   return (((int64_t)t * (m.d.Jp / 2) + (j >> 1)) * kTile + c) * 2 + (j & 1);

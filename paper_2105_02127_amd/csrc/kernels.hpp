@@ -236,48 +236,72 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// Least-squares phase over NR stencil rows starting at row R0; row s keeps
-// its operator entries at stored entries J0 + s*RS + l (RS even, entries
-// past the coefficient count are zero).  Each cell has LPC = 64 / kTile lanes
-// (g = 0..LPC-1); lane g gathers variable g % 4 of member r, forms
-// d = U_member - U_0 for all four variables by quad broadcast, and adds
-// M[l] d to acc[t][k][v] for the entry pairs p = g + LPC t it owns
-// (coefficients l = 2p + k), read with one 16-byte load per pair.  Rows are visited in order, so
-// every coefficient is summed over the rows in the same order as a plain
-// GEMV.
+// Least-squares phase (Sec. 2.2 eqs. 08-10) of one stencil as a stream of
+// its NR rows: a = M d with d_s = U_member(s) - U_0, row s of M^T stored at
+// entries J0 + s*RS .. (RS even; entries past the coefficient count are
+// zero).  Each cell has LPC = 64 / kTile lanes (g = 0..LPC-1); lane g gathers
+// variable g % 4 of the row's member, the four lanes share d for all four
+// variables by quad broadcast, and lane g adds the entry pairs p = g + LPC t
+// it owns (coefficients 2p and 2p+1, one 16-byte load each) into
+// acc[t][k][v].  Every entry is loaded by exactly one lane, and every
+// coefficient adds the rows one at a time in row order, as a plain GEMV does.
 //
 // Member indices come from LDS (staged once per tile), so a gather waits only
-// on the LDS counter.  The row loop is rolled and walks pairs of rows with
-// two fixed buffers: the loads of the next row are in flight while the
-// current row is accumulated, and no register ever changes role between
-// iterations (a rotating buffer would force a full wait every row; deeper
-// buffering or unrolling lets the compiler raise register use and lose
-// occupancy).
-// Pairs of stored entries per lane for a row of RS stored entries.
-template <int RS>
-constexpr int kSlots = (RS / 2 + kLanesPerCell - 1) / kLanesPerCell;
+// on the LDS counter.  NB row buffers live in fixed registers and the row
+// loop is unrolled by NB: while one row is accumulated the next NB-1 are in
+// flight, and no register changes role between iterations (a rotating
+// buffer would force a full wait every row).  prime() issues the first
+// NB-1 rows, so a caller can start the stream before it finishes other work.
+#ifndef TENO_ROW_BUFFERS
+#define TENO_ROW_BUFFERS 3
+#endif
+#ifndef TENO_M_NONTEMPORAL
+#define TENO_M_NONTEMPORAL 1
+#endif
 
 template <int R0, int NR, int J0, int RS>
-__device__ __forceinline__ void split_rows(const double* __restrict__ U, const int* sidx, int c,
-                                           const double2* __restrict__ mp, int g, double u0g,
-                                           double (&acc)[kSlots<RS>][2][4]) {
-  constexpr int NT = kSlots<RS>;
-  constexpr int LPC = kLanesPerCell;
-  constexpr int NPAIR = RS / 2;
-  const int v = g & 3;
-  auto issue = [&](int s, double& x, double2 (&m)[NT]) {
+struct RowStream {
+  static constexpr int NB = TENO_ROW_BUFFERS;
+  static constexpr int LPC = kLanesPerCell;
+  static constexpr int NPAIR = RS / 2;                // pairs per row
+  static constexpr int NT = (NPAIR + LPC - 1) / LPC;  // pair slots per lane
+  static_assert(RS % 2 == 0 && J0 % 2 == 0, "rows are whole pairs");
+  using Acc = double[NT][2][4];
+
+  const double* __restrict__ U;
+  const int* sidx;
+  const double2* __restrict__ mp;
+  int c, g;
+  double u0g;
+  double xq[NB];
+  double2 mq[NB][NT];
+
+  __device__ __forceinline__ void issue(int s, double& x, double2 (&m)[NT]) const {
+    s = s < NR ? s : NR - 1;  // loads past the last row re-read it (never used)
     const int r = R0 + s;
     const int id = sidx[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
-    x = U[(size_t)id * 4 + v];
+    x = U[(size_t)id * 4 + (g & 3)];
     const double2* __restrict__ mr = mp + (size_t)((J0 + s * RS) / 2) * kTile;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int pr = g + LPC * t;
-      m[t] = (LPC * t + LPC - 1 < NPAIR || pr < NPAIR) ? mr[(size_t)pr * kTile]
-                                                        : make_double2(0.0, 0.0);
+      // Lanes past the row's last pair re-read that pair: the load stays
+      // unconditional (a predicated load merged with a zero would make the
+      // compiler copy the buffers and wait for every load at the back edge),
+      // and the accumulators it feeds are never read.
+      const int pr = (LPC * t + LPC - 1 < NPAIR) ? g + LPC * t : min(g + LPC * t, NPAIR - 1);
+#if TENO_M_NONTEMPORAL
+      // operator entries are read once per stage: keep them out of the way
+      // of the gathered states in the caches
+      typedef double v2d __attribute__((ext_vector_type(2)));
+      const v2d w = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(&mr[(size_t)pr * kTile]));
+      m[t] = make_double2(w.x, w.y);
+#else
+      m[t] = mr[(size_t)pr * kTile];
+#endif
     }
-  };
-  auto accumulate = [&](double xv, const double2 (&m)[NT]) {
+  }
+
+  __device__ __forceinline__ void accumulate(double xv, const double2 (&m)[NT], Acc& acc) const {
     const double x = xv - u0g;
     const double d[4] = {quad_bcast<0>(x), quad_bcast<1>(x), quad_bcast<2>(x), quad_bcast<3>(x)};
 #pragma unroll
@@ -287,36 +311,43 @@ __device__ __forceinline__ void split_rows(const double* __restrict__ U, const i
         acc[t][0][q] = fma(m[t].x, d[q], acc[t][0][q]);
         acc[t][1][q] = fma(m[t].y, d[q], acc[t][1][q]);
       }
-  };
-  double xa, xb;
-  double2 ma[NT], mb[NT];
-  issue(0, xa, ma);
-  int s = 0;
-#pragma unroll 1
-  for (; s + 1 < NR; s += 2) {
-    issue(s + 1, xb, mb);
-    accumulate(xa, ma);
-    issue(s + 2 < NR ? s + 2 : NR - 1, xa, ma);  // clamped: stays inside the tile
-    accumulate(xb, mb);
   }
-  if (s < NR) accumulate(xa, ma);
-}
 
-// Coefficient L of variable v: pair L/2 is held by lane (L/2) % LPC of the
-// cell's lane group in slot (L/2) / LPC, component L % 2.
-template <int L, int NT>
-__device__ __forceinline__ double coef_of(const double (&acc)[NT][2][4], int v, int lane) {
-  constexpr int LPC = kLanesPerCell;
-  constexpr int src = (L / 2) % LPC, t = (L / 2) / LPC, k = L % 2;
-  if constexpr (LPC == 4) {
-    return pick4(quad_bcast<src>(acc[t][k][0]), quad_bcast<src>(acc[t][k][1]),
-                 quad_bcast<src>(acc[t][k][2]), quad_bcast<src>(acc[t][k][3]), v);
-  } else {
-    const int sl = (lane & ~(LPC - 1)) | src;
-    return pick4(__shfl(acc[t][k][0], sl), __shfl(acc[t][k][1], sl), __shfl(acc[t][k][2], sl),
-                 __shfl(acc[t][k][3], sl), v);
+  __device__ __forceinline__ void prime() {
+    static_for<0, NB - 1>([&](auto k) { issue(k, xq[k], mq[k]); });
   }
-}
+
+  // All rows into acc; prime() must have been called.
+  __device__ __forceinline__ void run(Acc& acc) {
+    int s = 0;
+#pragma unroll 1
+    for (; s + NB - 1 < NR; s += NB) {
+      static_for<0, NB>([&](auto k) {
+        constexpr int nb = (k + NB - 1) % NB;
+        issue(s + k + NB - 1, xq[nb], mq[nb]);
+        accumulate(xq[k], mq[k], acc);
+      });
+    }
+    static_for<0, NB - 1>([&](auto k) {
+      if (s + k < NR) accumulate(xq[k], mq[k], acc);
+    });
+  }
+
+  // Coefficient l (variable v): pair l/2 is held by lane (l/2) % LPC of the
+  // cell's lane group in slot (l/2) / LPC, component l % 2.
+  template <int l>
+  __device__ __forceinline__ static double coef(const Acc& acc, int v, int lane) {
+    constexpr int src = (l / 2) % LPC, t = (l / 2) / LPC, k = l % 2;
+    if constexpr (LPC == 4) {
+      return pick4(quad_bcast<src>(acc[t][k][0]), quad_bcast<src>(acc[t][k][1]),
+                   quad_bcast<src>(acc[t][k][2]), quad_bcast<src>(acc[t][k][3]), v);
+    } else {
+      const int sl = (lane & ~(LPC - 1)) | src;
+      return pick4(__shfl(acc[t][k][0], sl), __shfl(acc[t][k][1], sl), __shfl(acc[t][k][2], sl),
+                   __shfl(acc[t][k][3], sl), v);
+    }
+  }
+};
 
 // Occupancy target of the reconstruction kernel (waves per SIMD); 0 leaves
 // the register budget to the compiler.
@@ -367,26 +398,31 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   const bool frozen = a.frozen != 0;
   const unsigned nib_in = (frozen && live) ? ((a.flags[cell] >> (4 * v)) & 0xFu) : 8u;
 
-  // ---- small stencils (rows 0..32, entries 0..164), then step two of the
-  //      selection, which needs only their indicators ----
+  // ---- small stencils (rows 0..32), then step two of the selection, which
+  //      needs only their indicators.  Each stream is started before the
+  //      previous stencil's coefficients are gathered, and the large
+  //      stencil's first rows load during that last step ----
+  using LargeS = RowStream<33, O::NL, 3 * O::SBLK, stored_row(O::NU)>;
+  LargeS ls{a.U, sidx, mp, c, g, u0};
   double as[3][5];
   {
-    constexpr int NS = kSlots<O::SROW>;
-    {
-      double sk[NS][2][4] = {};
-      split_rows<0, 11, 0, O::SROW>(a.U, sidx, c, mp, g, u0, sk);
-      static_for<0, 5>([&](auto L) { as[0][L] = coef_of<L, NS>(sk, v, lane); });
-    }
-    {
-      double sk[NS][2][4] = {};
-      split_rows<11, 11, 11 * O::SROW, O::SROW>(a.U, sidx, c, mp, g, u0, sk);
-      static_for<0, 5>([&](auto L) { as[1][L] = coef_of<L, NS>(sk, v, lane); });
-    }
-    {
-      double sk[NS][2][4] = {};
-      split_rows<22, 11, 22 * O::SROW, O::SROW>(a.U, sidx, c, mp, g, u0, sk);
-      static_for<0, 5>([&](auto L) { as[2][L] = coef_of<L, NS>(sk, v, lane); });
-    }
+    using S0 = RowStream<0, 11, 0, stored_row(5)>;
+    using S1 = RowStream<11, 11, O::SBLK, stored_row(5)>;
+    using S2 = RowStream<22, 11, 2 * O::SBLK, stored_row(5)>;
+    S0 s0{a.U, sidx, mp, c, g, u0};
+    S1 s1{a.U, sidx, mp, c, g, u0};
+    S2 s2{a.U, sidx, mp, c, g, u0};
+    typename S0::Acc sk0 = {}, sk1 = {}, sk2 = {};
+    s0.prime();
+    s0.run(sk0);
+    s1.prime();
+    static_for<0, 5>([&](auto L) { as[0][L] = S0::template coef<L>(sk0, v, lane); });
+    s1.run(sk1);
+    s2.prime();
+    static_for<0, 5>([&](auto L) { as[1][L] = S1::template coef<L>(sk1, v, lane); });
+    s2.run(sk2);
+    ls.prime();
+    static_for<0, 5>([&](auto L) { as[2][L] = S2::template coef<L>(sk2, v, lane); });
   }
   unsigned nsm = nib_in & 7u;
   int ties_small = 0;
@@ -420,10 +456,9 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   // ---- large stencil (rows 33.., entries 165..) ----
   double aK[NU];
   {
-    constexpr int NT = kSlots<O::LROW>;
-    double sk[NT][2][4] = {};
-    split_rows<33, O::NL, 33 * O::SROW, O::LROW>(a.U, sidx, c, mp, g, u0, sk);
-    static_for<0, NU>([&](auto L) { aK[L] = coef_of<L, NT>(sk, v, lane); });
+    typename LargeS::Acc sk = {};
+    ls.run(sk);
+    static_for<0, NU>([&](auto L) { aK[L] = LargeS::template coef<L>(sk, v, lane); });
   }
   bool keepK = true;
   int ties = 0;
@@ -749,15 +784,13 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
     const double wk = (!keepK && (nib & (1u << k)) && cnt > 0) ? 1.0 / (double)cnt : 0.0;
 #pragma unroll
     for (int s = 0; s < 11; ++s) {
+      const int r = small_row(k, s);
       double d = 0.0;
 #pragma unroll
-      for (int l = 0; l < 5; ++l) {
-        const int j = k * 11 * O::SROW + s * O::SROW + l;
-        d = fma(entry(j), ab[l], d);
-      }
+      for (int l = 0; l < 5; ++l) d = fma(entry(k * O::SBLK + entry_in_block(5, s, l)), ab[l], d);
       d *= wk;
       dsum += d;
-      a.dbar[((size_t)(k * 11 + s) * a.n_pad + cell) * 4 + v] = d;
+      a.dbar[((size_t)r * a.n_pad + cell) * 4 + v] = d;
     }
   }
   const double wK = keepK ? 1.0 : 0.0;
@@ -766,7 +799,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
     double d = 0.0;
 #pragma unroll
     for (int l = 0; l < NU; ++l) {
-      const int j = 33 * O::SROW + s * O::LROW + l;
+      const int j = 3 * O::SBLK + entry_in_block(NU, s, l);
       d = fma(entry(j), ab[l], d);
     }
     d *= wK;

@@ -44,8 +44,8 @@ Dims dims_for(int order, int nq_req) {
   d.rows = 3 * kSmallRows + d.nl;
   d.rows4 = (d.rows + 3) / 4;
   d.J = 3 * kSmallCoef * kSmallRows + d.nu * d.nl;
-  d.lrow = d.nu + (d.nu & 1);
-  d.Jp = 3 * kSmallRows * kSmallStride + d.nl * d.lrow;
+  d.lblk = block_entries(d.nl, d.nu);
+  d.Jp = 3 * kSmallBlock + d.lblk;
   return d;
 }
 
@@ -488,7 +488,6 @@ int mesh_setup(Mesh& m, const teno_params& p) {
       const bool big = (k == 3);
       const Basis& B = big ? Bl : Bs;
       const int nrow = big ? d.nl : kSmallRows;
-      const int row0 = big ? 3 * kSmallRows : k * kSmallRows;
       auto report = [&](int code, const std::string& msg) {
         std::lock_guard<std::mutex> g(mu);
         if (i < err_cell) {
@@ -519,7 +518,7 @@ int mesh_setup(Mesh& m, const teno_params& p) {
       }
       rc_local = std::min(rc_local, rc);
       for (int s = 0; s < nrow; ++s) {
-        m.idx[packed_idx_index(m, t, row0 + s)] = m.inv[mem[s]];
+        m.idx[packed_idx_index(m, t, big ? large_row(s) : small_row(k, s))] = m.inv[mem[s]];
         for (int l = 0; l < B.n; ++l)
           m.M[packed_M_index(m, t, big ? entry_large(d, s, l) : entry_small(k, s, l))] =
               op[(size_t)l * nrow + s];

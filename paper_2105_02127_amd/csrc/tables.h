@@ -7,6 +7,8 @@
 // evaluated here at compile time.
 #pragma once
 
+#include "internal.h"
+
 namespace teno {
 
 constexpr double cx_fact(int n) {
@@ -133,9 +135,9 @@ struct OrderT {
   static constexpr int ROWS = 33 + NL;
   static constexpr int ROWS4 = (ROWS + 3) / 4;
   static constexpr int J = 165 + NU * NL;         // operator entries
-  static constexpr int LROW = NU + (NU & 1);       // stored large-row length
-  static constexpr int SROW = 6;                   // stored small-row length
-  static constexpr int JP = 3 * 11 * SROW + NL * LROW;  // stored entries
+  static constexpr int SBLK = block_entries(11, 5);    // stored entries per small stencil
+  static constexpr int LBLK = block_entries(NL, NU);    // stored large-stencil entries
+  static constexpr int JP = 3 * SBLK + LBLK;            // stored entries per cell
 };
 
 }  // namespace teno

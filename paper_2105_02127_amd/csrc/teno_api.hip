@@ -357,9 +357,9 @@ int teno_mesh_stencil(const teno_mesh* m, int32_t cell, int32_t k, int32_t* memb
   if (!x.ready) return fail(TENO_EARG, "teno_mesh_setup not called");
   if (cell < 0 || cell >= x.nc || k < 0 || k > 3) return fail(TENO_EARG, "cell or stencil out of range");
   const int t = x.inv[cell];
-  const int row0 = k == 3 ? 3 * kSmallRows : k * kSmallRows;
   const int nrow = k == 3 ? x.d.nl : kSmallRows;
-  for (int s = 0; s < nrow; ++s) members[s] = x.perm[x.idx[packed_idx_index(x, t, row0 + s)]];
+  for (int s = 0; s < nrow; ++s)
+    members[s] = x.perm[x.idx[packed_idx_index(x, t, k == 3 ? large_row(s) : small_row(k, s))]];
   return nrow;
 }
 
