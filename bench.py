@@ -23,6 +23,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = ("cell-updates/s per RK stage (5th-order, Euler) + HBM GB/s %peak; "
+          "adjoint/forward time")
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
@@ -255,8 +257,7 @@ def main():
     achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(w["name"])
     out = {
-        "metric": "cell-updates/s per RK stage (5th-order, Euler)" if order == 5 else
-                  f"cell-updates/s per RK stage ({order}th-order, Euler)",
+        "metric": METRIC if order == 5 else f"cell-updates/s per RK stage ({order}th-order, Euler)",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
