@@ -1,0 +1,97 @@
+"""Mutation check of the oracle's pins (CPU only).
+
+Each mutant plants one plausible mistake in a copy of the oracle source: a
+dropped term, a wrong sign, index or weight, a transposed operand.  The
+copy is built into a temporary library that the pin suite
+(`test_oracle_pins.py`) then loads through ORACLE_LIB; the pins must fail
+for every mutant.  The committed oracle is never modified.
+
+Alternative *readings* of the paper (the Roe sound-speed form, open or closed
+stencil cones, the stencil size) are deliberately not mutants: the paper's
+data cannot tell them apart, so no invariant pins them.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import build as oracle_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, exact text in the oracle source, replacement)
+MUTANTS = [
+    ("gauss_weight", "w[i] = 1.0 / ((1.0 - x * x) * dp * dp);",
+     "w[i] = 0.5 / ((1.0 - x * x) * dp * dp);"),
+    ("basis_mean", "return ipow(xi, b.ea[l]) * ipow(eta, b.eb[l]) - b.mean[l];",
+     "return ipow(xi, b.ea[l]) * ipow(eta, b.eb[l]) - 0.5 * b.mean[l];"),
+    ("qr_reflector", "double bta = 2.0 / vtv;", "double bta = 1.0 / vtv;"),
+    ("lsq_mean_volume", "S.qr.a[(size_t)l * want + s] = acc * a2 - S.vol[s] * B.mean[l];",
+     "S.qr.a[(size_t)l * want + s] = acc * a2 - B.mean[l];"),
+    ("lsq_rhs_volume", "b[s] = S.vol[s] * (U[4 * S.cells[s] + v] - u0);",
+     "b[s] = (U[4 * S.cells[s] + v] - u0);"),
+    ("beta_multiplicity", "      beta += acc;\n",
+     "      beta += (ax > 0 && ay > 0) ? 2.0 * acc : acc;\n"),
+    ("gamma_power", "return 1.0 / ipow(x, p.power);", "return 1.0 / ipow(x, p.power - 2);"),
+    ("cutoff_equality", "if (s.chiK >= p.ct) {", "if (s.chiK > p.ct) {"),
+    ("step_two_normalisation", "s.chi_small[k] = g[k] / sum_small;",
+     "s.chi_small[k] = g[k] / sum_all;"),
+    ("near_tie_absolute", "return std::fabs(chi / p.ct - 1.0) <= p.tie_rel;",
+     "return std::fabs(chi - p.ct) <= p.tie_rel;"),
+    ("small_weights", "abar[l] = acc / (double)cnt;", "abar[l] = acc;"),
+    ("face_point_direction", "else if (e == 1) { xi = 1.0 - t; eta = t; }",
+     "else if (e == 1) { xi = t; eta = 1.0 - t; }"),
+    ("hll_dissipation_sign", "SL * SR * (R[c] - L[c])", "SL * SR * (L[c] - R[c])"),
+    ("roe_weight", "T D = std::sqrt(R[0] / L[0]);", "T D = std::sqrt(L[0] / R[0]);"),
+    ("left_wave_speed", "T SL = min_re(unL - cL, ut - ct);", "T SL = min_re(unL - cL, ut + ct);"),
+    ("rotate_back", "out[1] = F[1] * nx - F[2] * ny;", "out[1] = F[1] * nx + F[2] * ny;"),
+    ("face_point_pairing",
+     "const T* uR = &fp[((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4];",
+     "const T* uR = &fp[((size_t)R * 3 * nq + eR * nq + k) * 4];"),
+    ("face_side_sign", "double s = (m.fL[f] == i && m.fLe[f] == e) ? 1.0 : -1.0;",
+     "double s = (m.fL[f] == i && m.fLe[f] == e) ? 1.0 : 1.0;"),
+    ("residual_sign", "Ri[c] = -acc[c] / m.area[i];", "Ri[c] = acc[c] / m.area[i];"),
+    ("dt_face_length", "den += m->flen[f] * (std::fabs(un) + c);", "den += (std::fabs(un) + c);"),
+    ("rk_stage_two", "U2[t] = 0.75 * U[t] + 0.25 * U1[t] + 0.25 * (dt * R[t]);",
+     "U2[t] = 0.25 * U[t] + 0.75 * U1[t] + 0.25 * (dt * R[t]);"),
+    ("vjp_face_adjoint",
+     "pb[c] = lam[4 * (size_t)R + c] / m->area[R] - lam[4 * (size_t)L + c] / m->area[L];",
+     "pb[c] = lam[4 * (size_t)R + c] / m->area[L] - lam[4 * (size_t)L + c] / m->area[R];"),
+    ("vjp_target_sign", "          Ubar[4 * (size_t)i + v] -= d;",
+     "          Ubar[4 * (size_t)i + v] += d;"),
+]
+
+
+def _run_mutant(tmp, name, old, new, src):
+    assert src.count(old) == 1, f"mutation site of {name} not found exactly once"
+    d = os.path.join(tmp, name)
+    os.makedirs(d, exist_ok=True)
+    cpp = os.path.join(d, "teno_oracle.cpp")
+    with open(cpp, "w") as fh:
+        fh.write(src.replace(old, new))
+    lib = os.path.join(d, "liboracle.so")
+    cmd = list(oracle_build.CMD)
+    cmd[cmd.index("-o") + 1] = lib
+    cmd[-1] = cpp
+    subprocess.run(cmd, check=True, capture_output=True)
+    env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-x", "-q", "-p", "no:cacheprovider", "-p", "no:randomly"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    last = (r.stdout.strip().splitlines() or [""])[-1]
+    return name, r.returncode, last
+
+
+def test_every_mutant_fails_a_pin(tmp_path):
+    src = open(oracle_build.SRC).read()
+    workers = max(1, min(4, (os.cpu_count() or 2) // 2))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(lambda m: _run_mutant(str(tmp_path), *m, src), MUTANTS))
+    survivors = [(n, last) for n, rc, last in results if rc == 0]
+    errors = [(n, rc, last) for n, rc, last in results if rc not in (0, 1)]
+    assert not errors, f"mutant runs that did not end in test failures: {errors}"
+    assert not survivors, f"mutants no pin detects: {survivors}"

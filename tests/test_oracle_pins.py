@@ -177,6 +177,30 @@ def test_selection_threshold_and_near_tie(oracle_mod):
     assert oracle_mod.select([0, 0, 0, hi], p)[2] == 0
 
 
+def test_selection_exact_equality_counts_as_smooth(oracle_mod):
+    # Sec. 3.3: a stencil is cut only when chi < C_T.  Four equal gammas of 1
+    # (beta = 1, eps = 0) give chi_K = 1/4 exactly; with C_T = 1/4 the large
+    # stencil stays.
+    p = oracle_mod.params(ct=0.25, eps=0.0)
+    fl, chi, _ = oracle_mod.select([1.0, 1.0, 1.0, 1.0], p)
+    assert chi[3] == 0.25 and fl == 8
+
+
+def test_selection_step_two_renormalises_small_stencils(oracle_mod):
+    # Sec. 3.3 step two divides each small gamma by the sum of the small
+    # gammas only.  gamma = (0.33, 0.33, 0.34, 0.25) with C_T = 0.3: chi_K =
+    # 0.2 sends the cell to step two, where chi'_k = 0.33, 0.33, 0.34 keep all
+    # three small stencils (a sum over all four gammas would give 0.264 ..
+    # 0.272 and keep none).
+    p = oracle_mod.params(ct=0.3)
+    g = np.array([0.33, 0.33, 0.34, 0.25])
+    beta = g ** (-1.0 / 6.0) - 1e-12
+    fl, chi, _ = oracle_mod.select(beta, p)
+    assert chi[3] == pytest.approx(0.2, rel=1e-12)
+    assert chi[:3] == pytest.approx([0.33, 0.33, 0.34], rel=1e-12)
+    assert fl == 7
+
+
 def test_selection_always_keeps_a_small_stencil(oracle_mod):
     rng = np.random.default_rng(1)
     p = oracle_mod.params()
