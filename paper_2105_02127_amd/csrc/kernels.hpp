@@ -736,14 +736,22 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
   }
 }
 
+// Adjoint of stencil row r of a cell: rows of a tile's 16 cells lie together
+// (512 contiguous bytes per row), so the rows that name one cell, which come
+// from its neighbourhood, sit in a few nearby tiles.
+__device__ __forceinline__ size_t dbar_index(int cell, int r, int rows4x4) {
+  return (((size_t)(cell / kTile) * rows4x4 + r) * kTile + cell % kTile) * 4;
+}
+
 // Phase 2 (one lane per (cell, variable)): transpose of the reconstruction.
 // Writes the adjoint of every stencil difference d_s = U_s - U_0 to
-// dbar[row][n_pad][4] and the cell's own direct part to own[n][4].
+// dbar (dbar_index: tile-local, each row's 16 cells together) and the cell's
+// own direct part to own[n][4].
 struct AdjReconArgs {
   const double* __restrict__ fpbar;
   const uint16_t* __restrict__ flags;
   const double2* __restrict__ M;
-  double* __restrict__ dbar;   // [rows4*4][n_pad][4]
+  double* __restrict__ dbar;   // [n_tiles][rows4*4][16][4]
   double* __restrict__ own;    // [n_pad][4]
   int n_cell, n_tiles, n_pad;
 };
@@ -790,7 +798,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
       for (int l = 0; l < 5; ++l) d = fma(entry(k * O::SBLK + entry_in_block(5, s, l)), ab[l], d);
       d *= wk;
       dsum += d;
-      a.dbar[((size_t)r * a.n_pad + cell) * 4 + v] = d;
+      a.dbar[dbar_index(cell, r, O::ROWS4 * 4) + v] = d;
     }
   }
   const double wK = keepK ? 1.0 : 0.0;
@@ -804,7 +812,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
     }
     d *= wK;
     dsum += d;
-    a.dbar[((size_t)(33 + s) * a.n_pad + cell) * 4 + v] = d;
+    a.dbar[dbar_index(cell, 33 + s, O::ROWS4 * 4) + v] = d;
   }
   a.own[(size_t)cell * 4 + v] = gsum - dsum;
 }
@@ -824,10 +832,36 @@ __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ o
 #pragma unroll
   for (int c = 0; c < 4; ++c) s[c] = own[(size_t)j * 4 + c];
   const int b = rev_ptr[j], e = rev_ptr[j + 1];
-  for (int t = b; t < e; ++t) {
-    const int ent = rev_ent[t];
+  // Entries are fetched GB at a time (all list entries, then all rows, each
+  // group in flight together) and then added in list order: the walk is a
+  // chain of dependent loads, so batching sets its length.
+  constexpr int GB = 8;
+  auto row_of = [&](int ent) {
     const int i = ent / rows4x4, r = ent - i * rows4x4;
-    const double2* d2 = reinterpret_cast<const double2*>(dbar + ((size_t)r * n_pad + i) * 4);
+    return reinterpret_cast<const double2*>(dbar + dbar_index(i, r, rows4x4));
+  };
+  int t = b;
+  for (; t + GB <= e; t += GB) {
+    int ent[GB];
+#pragma unroll
+    for (int k = 0; k < GB; ++k) ent[k] = rev_ent[t + k];
+    double2 x[GB], y[GB];
+#pragma unroll
+    for (int k = 0; k < GB; ++k) {
+      const double2* d2 = row_of(ent[k]);
+      x[k] = d2[0];
+      y[k] = d2[1];
+    }
+#pragma unroll
+    for (int k = 0; k < GB; ++k) {
+      s[0] += x[k].x;
+      s[1] += x[k].y;
+      s[2] += y[k].x;
+      s[3] += y[k].y;
+    }
+  }
+  for (; t < e; ++t) {
+    const double2* d2 = row_of(rev_ent[t]);
     const double2 x = d2[0], y = d2[1];
     s[0] += x.x;
     s[1] += x.y;
