@@ -104,6 +104,13 @@ def adjoint_timing(torch, teno, inputs, steps=200, checkpoint_every=20):
     area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
     wts = torch.as_tensor((area * inputs.disc_mask(mesh, center, radius))[lm.perm], device="cuda")
     adjoint.forward_rollout(sv, U0d, 5)          # warm-up
+    # warm-up backward over one checkpoint segment: the first backward
+    # allocates the segment's stage and face-state buffers (1.6 GB here),
+    # which later ones reuse from torch's caching allocator
+    xw = U0d.clone().requires_grad_(True)
+    UTw, _ = adjoint.rollout(sv, xw, checkpoint_every, checkpoint_every=checkpoint_every)
+    adjoint.pressure_squared_loss(UTw, wts).backward()
+    del xw, UTw
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     adjoint.forward_rollout(sv, U0d, steps, checkpoint_every=checkpoint_every)

@@ -68,6 +68,8 @@ typedef struct teno_info {
   int64_t matrix_doubles_per_cell;   /* streamed pseudo-inverse entries      */
   int64_t device_bytes;              /* library-owned device memory          */
   double min_rcond;                  /* min over stencils of min|R_jj|/max|R_jj| */
+  int64_t face_state_doubles;        /* one stage's face states in the library  */
+                                     /* layout (teno_rk_step, teno_vjp_rk_step) */
 } teno_info;
 
 /* Device-side diagnostics, accumulated until reset. */
@@ -156,9 +158,13 @@ int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk,
 /* One full SSP-RK3 step in place on U using library-owned stage buffers.
  * flags3: nullable device uint16_t[3][n_cell] (out, or in when frozen != 0).
  * stages: nullable device double[3][n_cell][4], receives the stage inputs
- * U^n, U^(1), U^(2) (what the adjoint needs). */
+ * U^n, U^(1), U^(2) (what the adjoint needs).
+ * face_states3: nullable device double[3][face_state_doubles] (teno_info);
+ * when given, each stage's face Gauss-point states are computed into it (in
+ * the library's layout, opaque to the caller) and kept for
+ * teno_vjp_rk_step. */
 int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flags3,
-                 int32_t frozen, double* stages, void* stream);
+                 int32_t frozen, double* stages, double* face_states3, void* stream);
 
 /* Adjoint of the residual with the selection frozen to `flags`:
  * U_bar = (dR/dU)^T lam.  The reconstruction is linear in U for fixed
@@ -168,9 +174,12 @@ int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, co
 
 /* Adjoint of one SSP-RK3 step (frozen dt and selection): given the stage
  * inputs (teno_rk_step's `stages`), their flags3 and lam_out = adjoint of
- * U^{n+1}, writes lam_in = adjoint of U^n.  lam_in may alias lam_out. */
+ * U^{n+1}, writes lam_in = adjoint of U^n.  lam_in may alias lam_out.
+ * face_states3: nullable; the face states teno_rk_step kept for these
+ * stages, which saves reconstructing them (same result either way). */
 int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags3,
-                     const double* dt_dev, const double* lam_out, double* lam_in, void* stream);
+                     const double* face_states3, const double* dt_dev, const double* lam_out,
+                     double* lam_in, void* stream);
 
 /* Reads (and optionally resets) the device diagnostics; synchronises the
  * stream. */

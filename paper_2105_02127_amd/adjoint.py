@@ -8,8 +8,9 @@ device (HLL Jacobian by forward-mode dual numbers, reconstruction transposed
 by a reverse-stencil gather, no atomics).
 
 Memory: U is checkpointed every `checkpoint_every` steps; the backward pass
-recomputes one segment at a time (its stage states and flags) and walks it
-backwards.
+recomputes one segment at a time (its stage states, flags and, unless
+`keep_face_states` is off, the face states of every stage, which spares the
+adjoint a reconstruction per stage) and walks it backwards.
 """
 from __future__ import annotations
 
@@ -52,7 +53,7 @@ class RK3Rollout(torch.autograd.Function):
     selection."""
 
     @staticmethod
-    def forward(ctx, U0, solver, n_steps, cfl, checkpoint_every, dts):
+    def forward(ctx, U0, solver, n_steps, cfl, checkpoint_every, dts, keep_face_states=True):
         U, dts_used, ckpts = forward_rollout(solver, U0, n_steps, cfl, dts, checkpoint_every)
         if dts is not None:
             dts_used = dts_used.clone()
@@ -61,6 +62,7 @@ class RK3Rollout(torch.autograd.Function):
         ctx.K = checkpoint_every
         ctx.dts = dts_used
         ctx.ckpts = ckpts
+        ctx.keep = keep_face_states
         ctx.mark_non_differentiable(dts_used)
         return U, dts_used
 
@@ -72,20 +74,25 @@ class RK3Rollout(torch.autograd.Function):
         dev = lam.device
         stages = torch.empty((K, 3, nc, 4), dtype=torch.float64, device=dev)
         flags = torch.empty((K, 3, nc), dtype=torch.int16, device=dev)
+        fs = sv.empty_face_states(K) if ctx.keep else None
         for seg in reversed(range(len(ctx.ckpts))):
             s0 = seg * K
             s1 = min(n, s0 + K)
             U = ctx.ckpts[seg].clone()
             for s in range(s0, s1):     # recompute the segment, keeping its stages
-                sv.rk_step(U, ctx.dts[s:s + 1], flags3=flags[s - s0], stages=stages[s - s0])
+                sv.rk_step(U, ctx.dts[s:s + 1], flags3=flags[s - s0], stages=stages[s - s0],
+                           face_states=None if fs is None else fs[s - s0])
             for s in reversed(range(s0, s1)):
-                sv.vjp_rk_step(stages[s - s0], flags[s - s0], ctx.dts[s:s + 1], lam, lam)
-        return lam, None, None, None, None, None
+                sv.vjp_rk_step(stages[s - s0], flags[s - s0], ctx.dts[s:s + 1], lam, lam,
+                               face_states=None if fs is None else fs[s - s0])
+        return lam, None, None, None, None, None, None
 
 
-def rollout(solver, U0, n_steps, cfl=0.4, checkpoint_every=20, dts=None):
-    """Differentiable rollout: returns (U_final, dts)."""
-    return RK3Rollout.apply(U0, solver, n_steps, cfl, checkpoint_every, dts)
+def rollout(solver, U0, n_steps, cfl=0.4, checkpoint_every=20, dts=None, keep_face_states=True):
+    """Differentiable rollout: returns (U_final, dts).  keep_face_states
+    trades 3 * face_state_doubles * 8 bytes per checkpointed step of device
+    memory for one reconstruction per stage of the backward pass."""
+    return RK3Rollout.apply(U0, solver, n_steps, cfl, checkpoint_every, dts, keep_face_states)
 
 
 def pressure_squared_loss(U, weights, gamma=1.4):

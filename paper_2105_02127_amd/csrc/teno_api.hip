@@ -151,13 +151,18 @@ int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
   return TENO_OK;
 }
 
+// Doubles of one stage's face states in the library layout [3 nq][n_pad][4].
+static size_t face_state_doubles(const teno_solver* s) { return (size_t)3 * s->d.nq * s->n_pad * 4; }
+
+// fp: face-state buffer of the launch (library layout), nullptr = the
+// solver's own.
 int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool frozen,
-                       hipStream_t st) {
+                       hipStream_t st, double* fp = nullptr) {
   ReconArgs a;
   a.U = U;
   a.idx = s->idx;
   a.M = s->M;
-  a.fp = s->fp;
+  a.fp = fp ? fp : s->fp;
   a.flags = flags;
   a.user_of = s->user_of;
   a.diag = s->diag;
@@ -184,9 +189,10 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
 }
 
 int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
-                const double* dt, double ca, double cb, double cc, bool rk, hipStream_t st) {
+                const double* dt, double ca, double cb, double cc, bool rk, hipStream_t st,
+                const double* fp = nullptr) {
   FluxArgs a;
-  a.fp = s->fp;
+  a.fp = fp ? fp : s->fp;
   a.nbinfo = s->nbinfo;
   a.geo = s->geo;
   a.Un = Un;
@@ -225,13 +231,18 @@ int launch_dt(teno_solver* s, const double* U, double cfl, double* dt, hipStream
 }
 
 // U_bar = scale * dt_scale * (dR/dU)^T lam + beta * extra, selection frozen.
+// fp_in: the face states of U under `flags` (library layout) when the caller
+// kept them from the forward pass; nullptr reconstructs them here.
 int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
                const double* scale_dev, double scale, const double* extra, double beta,
-               double* out, hipStream_t st) {
-  int rc = launch_reconstruct(s, U, const_cast<uint16_t*>(flags), true, st);
-  if (rc) return rc;
+               double* out, hipStream_t st, const double* fp_in = nullptr) {
+  int rc = TENO_OK;
+  if (!fp_in) {
+    rc = launch_reconstruct(s, U, const_cast<uint16_t*>(flags), true, st);
+    if (rc) return rc;
+  }
   AdjArgs fa;
-  fa.fp = s->fp;
+  fa.fp = fp_in ? fp_in : s->fp;
   fa.nbinfo = s->nbinfo;
   fa.geo = s->geo;
   fa.lam = lam;
@@ -340,6 +351,7 @@ int teno_mesh_info(const teno_mesh* m, teno_info* out) {
     out->rows_small = kSmallRows;
     out->matrix_doubles_per_cell = x.d.J;
     out->min_rcond = x.min_rcond;
+    out->face_state_doubles = (int64_t)3 * x.d.nq * x.n_pad * 4;
   }
   return TENO_OK;
 }
@@ -511,10 +523,11 @@ int teno_max_dt(teno_solver* s, const double* U, double cfl, double* dt_dev, voi
 
 
 static int stage_impl(teno_solver* s, int k, const double* Un, const double* Uk, double* Uk1,
-                      const double* dt, uint16_t* flags, bool frozen, hipStream_t st) {
-  int rc = launch_reconstruct(s, Uk, flags, frozen, st);
+                      const double* dt, uint16_t* flags, bool frozen, hipStream_t st,
+                      double* fp = nullptr) {
+  int rc = launch_reconstruct(s, Uk, flags, frozen, st, fp);
   if (rc) return rc;
-  return launch_flux(s, Un, Uk, Uk1, dt, kStageA[k], kStageB[k], kStageC[k], true, st);
+  return launch_flux(s, Un, Uk, Uk1, dt, kStageA[k], kStageB[k], kStageC[k], true, st, fp);
 }
 
 int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk, double* Uk1,
@@ -530,7 +543,7 @@ int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk,
 }
 
 int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flags3,
-                 int32_t frozen, double* stages, void* stream) {
+                 int32_t frozen, double* stages, double* face_states3, void* stream) {
   if (int rc = check_solver(s)) return rc;
   if (!U || !dt_dev) return fail(TENO_EARG, "null argument");
   if (frozen && !flags3) return fail(TENO_EARG, "frozen selection needs flags3");
@@ -539,23 +552,25 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
   const size_t n = (size_t)s->n_cell;
   const size_t nb = n * 4 * sizeof(double);
   auto fl = [&](int k) { return flags3 ? flags3 + (size_t)k * n : nullptr; };
+  const size_t fsz = face_state_doubles(s);
+  auto fs = [&](int k) { return face_states3 ? face_states3 + (size_t)k * fsz : nullptr; };
   if (stages) {
     hipError_t e = hipMemcpyAsync(stages, U, nb, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   }
-  int rc = stage_impl(s, 0, U, U, s->W1, dt_dev, fl(0), frozen != 0, st);
+  int rc = stage_impl(s, 0, U, U, s->W1, dt_dev, fl(0), frozen != 0, st, fs(0));
   if (rc) return rc;
   if (stages) {
     hipError_t e = hipMemcpyAsync(stages + n * 4, s->W1, nb, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   }
-  rc = stage_impl(s, 1, U, s->W1, s->W2, dt_dev, fl(1), frozen != 0, st);
+  rc = stage_impl(s, 1, U, s->W1, s->W2, dt_dev, fl(1), frozen != 0, st, fs(1));
   if (rc) return rc;
   if (stages) {
     hipError_t e = hipMemcpyAsync(stages + 2 * n * 4, s->W2, nb, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   }
-  return stage_impl(s, 2, U, s->W2, U, dt_dev, fl(2), frozen != 0, st);
+  return stage_impl(s, 2, U, s->W2, U, dt_dev, fl(2), frozen != 0, st, fs(2));
 }
 
 int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
@@ -568,7 +583,8 @@ int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, co
 }
 
 int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags3,
-                     const double* dt_dev, const double* lam_out, double* lam_in, void* stream) {
+                     const double* face_states3, const double* dt_dev, const double* lam_out,
+                     double* lam_in, void* stream) {
   if (int rc = check_solver(s)) return rc;
   if (!stages || !flags3 || !dt_dev || !lam_out || !lam_in) return fail(TENO_EARG, "null argument");
   DeviceScope ds(s->device);
@@ -577,15 +593,17 @@ int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags
   const double* U0 = stages;
   const double* U1 = stages + n * 4;
   const double* U2 = stages + 2 * n * 4;
+  const size_t fsz = face_state_doubles(s);
+  auto fs = [&](int k) { return face_states3 ? face_states3 + (size_t)k * fsz : nullptr; };
   // U' = 1/3 U0 + 2/3 U2 + 2/3 dt R(U2)   ->  T2 = lam_2 (adjoint of U2)
   int rc = launch_vjp(s, U2, flags3 + 2 * n, lam_out, dt_dev, 2.0 / 3.0, lam_out, 2.0 / 3.0,
-                      s->T2, st);
+                      s->T2, st, fs(2));
   if (rc) return rc;
   // U2 = 3/4 U0 + 1/4 U1 + 1/4 dt R(U1)  ->  T1 = lam_1
-  rc = launch_vjp(s, U1, flags3 + n, s->T2, dt_dev, 0.25, s->T2, 0.25, s->T1, st);
+  rc = launch_vjp(s, U1, flags3 + n, s->T2, dt_dev, 0.25, s->T2, 0.25, s->T1, st, fs(1));
   if (rc) return rc;
   // U1 = U0 + dt R(U0)                   ->  T0 = lam_1 + dt R'(U0)^T lam_1
-  rc = launch_vjp(s, U0, flags3, s->T1, dt_dev, 1.0, s->T1, 1.0, s->T0, st);
+  rc = launch_vjp(s, U0, flags3, s->T1, dt_dev, 1.0, s->T1, 1.0, s->T0, st, fs(0));
   if (rc) return rc;
   return lincomb(s, lam_in, 1.0 / 3.0, lam_out, 0.75, s->T2, 1.0, s->T0, st);
 }

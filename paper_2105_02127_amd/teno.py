@@ -30,7 +30,7 @@ class Info(C.Structure):
                 ("n_quad", C.c_int32), ("n_coef_large", C.c_int32), ("rows_large", C.c_int32),
                 ("n_coef_small", C.c_int32), ("rows_small", C.c_int32),
                 ("matrix_doubles_per_cell", C.c_int64), ("device_bytes", C.c_int64),
-                ("min_rcond", C.c_double)]
+                ("min_rcond", C.c_double), ("face_state_doubles", C.c_int64)]
 
 
 class BatchTuning(C.Structure):
@@ -62,9 +62,9 @@ SIGNATURES = {
     "teno_reconstruct": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "teno_max_dt": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
     "teno_rk_stage": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
-    "teno_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "teno_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     "teno_vjp_residual": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
-    "teno_vjp_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "teno_vjp_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "teno_diagnostics": (C.c_int, [_vp, C.POINTER(Diag), _i32, _vp]),
     "teno_profile_enable": (C.c_int, [_vp, _i32]),
     "teno_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64), _i32]),
@@ -239,6 +239,7 @@ class Solver:
         self.n_cell = info.n_cell
         self.n_quad = info.n_quad
         self.order = info.order
+        self.face_state_doubles = int(info.face_state_doubles)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -306,12 +307,25 @@ class Solver:
                                     1 if frozen else 0, _stream(stream)))
         return Uk1
 
-    def rk_step(self, U, dt, flags3=None, frozen=False, stages=None, stream=None):
+    def empty_face_states(self, n_steps=None):
+        """Buffer for the face states rk_step can keep for vjp_rk_step:
+        [3, face_state_doubles] float64 (or [n_steps, 3, ...])."""
+        import torch
+        shape = (3, self.face_state_doubles) if n_steps is None else \
+            (n_steps, 3, self.face_state_doubles)
+        return torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def _face_states(self, t):
+        import torch
+        return _ptr(t, (3, self.face_state_doubles), torch.float64, "face_states", True)
+
+    def rk_step(self, U, dt, flags3=None, frozen=False, stages=None, face_states=None,
+                stream=None):
         import torch
         st = None if stages is None else _ptr(stages, (3, self.n_cell, 4), torch.float64, "stages")
         _check(load().teno_rk_step(self.h, self._state(U, "U"), self._dt(dt),
                                    self._flags(flags3, 3, "flags3"), 1 if frozen else 0, st,
-                                   _stream(stream)))
+                                   self._face_states(face_states), _stream(stream)))
         return U
 
     def vjp_residual(self, U, flags, lam, U_bar=None, stream=None):
@@ -322,13 +336,15 @@ class Solver:
                                         _stream(stream)))
         return U_bar
 
-    def vjp_rk_step(self, stages, flags3, dt, lam_out, lam_in=None, stream=None):
+    def vjp_rk_step(self, stages, flags3, dt, lam_out, lam_in=None, face_states=None,
+                    stream=None):
         import torch
         lam_in = self.empty_state() if lam_in is None else lam_in
         _check(load().teno_vjp_rk_step(
             self.h, _ptr(stages, (3, self.n_cell, 4), torch.float64, "stages"),
-            self._flags(flags3, 3, "flags3", nullable=False), self._dt(dt),
-            self._state(lam_out, "lam_out"), self._state(lam_in, "lam_in"), _stream(stream)))
+            self._flags(flags3, 3, "flags3", nullable=False), self._face_states(face_states),
+            self._dt(dt), self._state(lam_out, "lam_out"), self._state(lam_in, "lam_in"),
+            _stream(stream)))
         return lam_in
 
     def diagnostics(self, reset=False, stream=None) -> dict:

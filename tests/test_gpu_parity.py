@@ -258,6 +258,18 @@ def test_vjp_rk_step_matches_oracle(teno, oracle_mod, torch_cuda):
     got = c.sv.vjp_rk_step(st, f3, dt, c.dev(lam))
     torch.cuda.synchronize()
     assert_states(c.host_user(got), ref, rel=1e-11, what="lam_in")
+    # face states kept by a GPU step under the same selection and dt spare
+    # the adjoint its reconstructions; the result must not change
+    fs = c.sv.empty_face_states()
+    U = c.dev(base["stages"][0])
+    st2 = torch.empty_like(st)
+    f32 = torch.empty_like(f3)
+    c.sv.rk_step(U, dt, flags3=f32, stages=st2, face_states=fs)
+    kept = c.sv.vjp_rk_step(st2, f32, dt, c.dev(lam), face_states=fs)
+    again = c.sv.vjp_rk_step(st2, f32, dt, c.dev(lam))
+    torch.cuda.synchronize()
+    assert torch.equal(kept, again)
+    assert_states(c.host_user(kept), ref, rel=1e-10, what="lam_in (kept face states)")
 
 
 # --------------------------------------------------------------------------
