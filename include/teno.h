@@ -185,10 +185,12 @@ int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags
  * stream. */
 int teno_diagnostics(teno_solver* s, teno_diag* out, int32_t reset, void* stream);
 
-/* Kernel timing with HIP events around every launch (off by default).
- * teno_profile_read returns, per kernel kind (0 reconstruct, 1 flux+update,
- * 2 dt, 3 adjoint), the summed milliseconds and launch counts; synchronises. */
-int teno_profile_enable(teno_solver* s, int32_t on);
+/* Kernel timing with HIP events around the launches of the selected kinds
+ * (off by default).  kinds: bit k selects kind k (0 reconstruct, 1 flux +
+ * update, 2 dt, 3 adjoint); 0 turns timing off, 15 times everything.
+ * teno_profile_read returns, per kind, the summed milliseconds and launch
+ * counts; synchronises. */
+int teno_profile_enable(teno_solver* s, int32_t kinds);
 int teno_profile_read(teno_solver* s, double* ms, int64_t* launches, int32_t reset);
 
 /* ---- batch of independent meshes --------------------------------------- */

@@ -91,7 +91,7 @@ struct teno_solver {
   std::vector<void*> allocs;
   int64_t bytes = 0;
   // profiling
-  bool prof = false;
+  unsigned prof = 0;  // bit k: time kernels of kind k
   struct Ev {
     int kind;
     hipEvent_t a, b;
@@ -127,11 +127,12 @@ struct teno_solver {
 
 namespace {
 
-// Records kernel timing around `launch` when profiling is on.
+// Records kernel timing around `launch` when profiling is on for `kind`.
 template <class F>
 int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  if (s->prof) {
+  const bool on = (s->prof >> kind) & 1;
+  if (on) {
     if (!s->pool.empty()) {
       ev = s->pool.back();
       s->pool.pop_back();
@@ -144,7 +145,7 @@ int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
   launch();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  if (s->prof) {
+  if (on) {
     (void)hipEventRecord(ev.second, st);
     s->evs.push_back({kind, ev.first, ev.second});
   }
@@ -629,9 +630,9 @@ int teno_diagnostics(teno_solver* s, teno_diag* out, int32_t reset, void* stream
   return TENO_OK;
 }
 
-int teno_profile_enable(teno_solver* s, int32_t on) {
+int teno_profile_enable(teno_solver* s, int32_t kinds) {
   if (int rc = check_solver(s)) return rc;
-  s->prof = on != 0;
+  s->prof = (unsigned)kinds & 0xFu;
   return TENO_OK;
 }
 

@@ -352,8 +352,18 @@ class Solver:
         _check(load().teno_diagnostics(self.h, C.byref(d), 1 if reset else 0, _stream(stream)))
         return {k: int(getattr(d, k)) for k, _ in Diag._fields_}
 
-    def profile_enable(self, on=True):
-        _check(load().teno_profile_enable(self.h, 1 if on else 0))
+    def profile_enable(self, on=True, kinds=None):
+        """Times the launches of `kinds` (names from KERNEL_KINDS; all when
+        None) with HIP events while `on`."""
+        if not on:
+            mask = 0
+        elif kinds is None:
+            mask = 0xF
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << KERNEL_KINDS.index(k)
+        _check(load().teno_profile_enable(self.h, mask))
 
     def profile_read(self, reset=True) -> ProfileReading:
         ms = (C.c_double * 4)()
