@@ -132,26 +132,40 @@ __device__ __forceinline__ Dual<N> dsqrt(const Dual<N>& a) {
   return r;
 }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+template <int N>
+__device__ __forceinline__ Dual<N> recip(const Dual<N>& a) {
+  Dual<N> r;
+  r.v = 1.0 / a.v;
+  const double r2 = r.v * r.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i] * r2;
+  return r;
+}
 template <int N>
 __device__ __forceinline__ double vof(const Dual<N>& a) { return a.v; }
 __device__ __forceinline__ double vof(double a) { return a; }
 
 // HLL flux through unit normal (nx, ny): rotate into the face frame, HLL with
 // S_L = min(u_L - c_L, u~ - c~), S_R = max(u_R + c_R, u~ + c~) from Roe
-// averages (both velocity components in c~), rotate back.
+// averages (both velocity components in c~), rotate back.  The quotients
+// share four reciprocals (1/rho_L, 1/rho_R, 1/(1 + sqrt(rho_R/rho_L)),
+// 1/(S_R - S_L)): FP64 division is a long instruction sequence and this
+// function is most of the flux kernel's work.
 template <class T>
 __device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, double ny, double g,
                                     T out[4]) {
   const T L0 = uL[0], L1 = nx * uL[1] + ny * uL[2], L2 = nx * uL[2] + (-ny) * uL[1], L3 = uL[3];
   const T R0 = uR[0], R1 = nx * uR[1] + ny * uR[2], R2 = nx * uR[2] + (-ny) * uR[1], R3 = uR[3];
-  const T unL = L1 / L0, utL = L2 / L0, unR = R1 / R0, utR = R2 / R0;
+  const T iL = recip(L0), iR = recip(R0);
+  const T unL = L1 * iL, utL = L2 * iL, unR = R1 * iR, utR = R2 * iR;
   const T pL = (g - 1.0) * (L3 - (0.5 * L0) * (unL * unL + utL * utL));
   const T pR = (g - 1.0) * (R3 - (0.5 * R0) * (unR * unR + utR * utR));
-  const T cL = dsqrt(g * pL / L0), cR = dsqrt(g * pR / R0);
-  const T HL = (L3 + pL) / L0, HR = (R3 + pR) / R0;
-  const T D = dsqrt(R0 / L0);
-  const T den = 1.0 + D;
-  const T ut = (unL + D * unR) / den, vt = (utL + D * utR) / den, Ht = (HL + D * HR) / den;
+  const T cL = dsqrt(g * pL * iL), cR = dsqrt(g * pR * iR);
+  const T HL = (L3 + pL) * iL, HR = (R3 + pR) * iR;
+  const T D = dsqrt(R0 * iL);
+  const T iden = recip(1.0 + D);
+  const T ut = (unL + D * unR) * iden, vt = (utL + D * utR) * iden, Ht = (HL + D * HR) * iden;
   const T ct = dsqrt((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)));
   const T a1 = unL - cL, a2 = ut - ct;
   const T SL = vof(a2) < vof(a1) ? a2 : a1;
@@ -169,9 +183,9 @@ __device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, dou
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[c] = FR[c];
   } else {
-    const T inv = SR - SL;
+    const T iS = recip(SR - SL);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) F[c] = (SR * FL[c] - SL * FR[c] + SL * SR * (UR[c] - UL[c])) / inv;
+    for (int c = 0; c < 4; ++c) F[c] = (SR * FL[c] - SL * FR[c] + SL * SR * (UR[c] - UL[c])) * iS;
   }
   out[0] = F[0];
   out[1] = nx * F[1] - ny * F[2];
@@ -578,10 +592,10 @@ __device__ __forceinline__ void flux_cell(const FluxArgs& a, int t) {
       acc[c] = isL ? acc[c] + p : acc[c] - p;
     }
   }
-  const double area = g[9];
+  const double ia = -1.0 / g[9];
   double R[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) R[c] = -acc[c] / area;
+  for (int c = 0; c < 4; ++c) R[c] = acc[c] * ia;
   double* o = a.out + (size_t)t * 4;
   if (RK) {
     const double dt = *a.dt;

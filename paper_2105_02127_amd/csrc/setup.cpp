@@ -440,6 +440,10 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   m.d = dims_for(p.order, p.n_quad);
   const Dims& d = m.d;
   const int nc = m.nc;
+  // stencil rows are addressed as cell * 4 ceil(rows / 4) + row in 32 bits
+  if ((int64_t)(nc + kTile) * d.rows4 * 4 >= (int64_t)INT32_MAX)
+    return fail(TENO_EARG, "mesh too large: " + std::to_string(nc) + " cells at order " +
+                               std::to_string(p.order) + " exceed 32-bit stencil-row indices");
 
   // ---- cell order ----
   m.perm.resize(nc);

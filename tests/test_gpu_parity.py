@@ -226,6 +226,29 @@ def test_deterministic_and_conservative(teno, oracle_mod, torch_cuda):
     assert np.abs(tot).max() <= 1e-13 * (a[:, None] * R1).abs().sum(0).max().item()
 
 
+@pytest.mark.parametrize("order", [3, 6])
+def test_free_stream(teno, oracle_mod, torch_cuda, order):
+    # Sec. 2.1: a uniform state is a steady solution.  Every stencil
+    # difference is zero, so beta = 0, the large stencil is kept for every
+    # variable (chi_K = 1/4), the face states equal the average, and the
+    # residual cancels to round-off (relative to the flux scale).
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 15, 81, order, oracle_all=False)
+    rho, u, v, p = 1.3, 0.7, -0.4, 0.9
+    U = inputs.conservative(np.full(c.m.n_cell, rho), np.full(c.m.n_cell, u),
+                            np.full(c.m.n_cell, v), np.full(c.m.n_cell, p))
+    Ud = torch.as_tensor(U[c.perm], device="cuda")
+    flags = torch.empty(c.m.n_cell, dtype=torch.int16, device="cuda")
+    fs = c.sv.reconstruct(Ud, flags=flags)
+    R = c.sv.residual(Ud)
+    torch.cuda.synchronize()
+    assert set(np.unique(c.flags_user(flags)).tolist()) == {0x8888}
+    assert torch.equal(fs, Ud[None].expand_as(fs))
+    c.U = U
+    assert np.abs(R.cpu().numpy()).max() <= 1e-13 * c.flux_scale()
+    assert c.sv.diagnostics(reset=True)["near_ties"] == 0
+
+
 def test_dt_matches_oracle(teno, oracle_mod, torch_cuda):
     torch = torch_cuda
     c = Case(teno, oracle_mod, torch, 21, 71, 3, oracle_all=False)
