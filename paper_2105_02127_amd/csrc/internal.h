@@ -67,6 +67,12 @@ struct Mesh {
   std::vector<int32_t> nbinfo;  // [n_pad][4]: 3 neighbours + packed edge/side bits
   std::vector<double> geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area
   std::vector<int32_t> user_of; // [n_pad] user id (diagnostics)
+  // face-ordered flux data: faces sorted by their L cell's internal index
+  std::vector<int32_t> face_cells;  // [nf][4]: L, R (internal), eL | eR << 2, 0
+  std::vector<double> face_geo;     // [nf][4]: nx, ny (out of L), |A|, 0
+  std::vector<int32_t> cell_faces;  // [n_pad][4]: sorted face of local edges 0..2;
+                                    //   bit e of [3] set when the cell is that face's L
+  std::vector<double> vol;          // [n_pad] |V| (1 for padding cells)
   // reverse stencil (adjoint gather): cells i whose row r names cell j
   std::vector<int32_t> rev_ptr; // [n_cell + 1]
   std::vector<int32_t> rev_ent; // i * rows4*4 + r, internal ids

@@ -13,13 +13,12 @@
 //                  (Sec. 2.3), the strong scale separation and the two-step
 //                  ENO-like selection (Sec. 3.2-3.3), and the face
 //                  Gauss-point states, written once.
-//  k_flux_update   one lane per cell: rotated HLL flux with Einfeldt/Roe wave
-//                  speeds (Sec. 4) on the cell's three faces from its own and
-//                  its neighbours' face states, face quadrature, gather into
-//                  the residual (Sec. 2.1), optional SSP-RK3 stage combine.
-//                  Each face flux is evaluated by both of its cells from
-//                  identical inputs in identical order, so the two
-//                  contributions cancel exactly (no atomics, deterministic).
+//  k_face_flux     one lane per face: rotated HLL flux with Einfeldt/Roe wave
+//                  speeds (Sec. 4) at the face's Gauss point pairs and the
+//                  face quadrature, written once per face.
+//  k_cell_update   one lane per cell: gather of its three face fluxes into
+//                  the residual (Sec. 2.1), optional SSP-RK3 stage combine
+//                  (a gather in a fixed order: no atomics, deterministic).
 //  k_dt_*          constant-CFL step: per-block minima, then one block.
 //  k_adj_*         adjoint of the residual with the selection frozen.
 //
@@ -544,55 +543,80 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
 // ---------------------------------------------------------------------------
 // flux, residual, Runge-Kutta stage
 // ---------------------------------------------------------------------------
-struct FluxArgs {
+// Flux and residual (Sec. 2.1, Sec. 4), in two launches.
+//  face_flux    one lane per face (faces sorted by their L cell): rotated HLL
+//               at the N_q point pairs (L point k with R point N_q-1-k),
+//               Gauss quadrature, Phi_f = |A| sum_k w_k F_k, written once.
+//  cell_update  one lane per cell: R = -(1/|V|) sum_e s_e Phi_f(e) over its
+//               three faces in local-edge order (s = +1 on the L side), then
+//               the optional SSP-RK3 stage combine.  A gather: no atomics.
+struct FaceFluxArgs {
   const double* __restrict__ fp;       // [3 nq][n_pad][4]
-  const int4* __restrict__ nbinfo;     // [n_pad]
-  const double* __restrict__ geo;      // [n_pad][10]
+  const int4* __restrict__ fcell;      // [n_face]: L, R, eL | eR << 2
+  const double2* __restrict__ fgeo;    // [n_face][2]: (nx, ny), (|A|, 0)
+  double* __restrict__ phi;            // [n_face][4]
+  double gamma;
+  int n_face, n_pad;
+};
+
+template <int NQ>
+__device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f) {
+  const int4 fc = a.fcell[f];
+  const double2 nrm = a.fgeo[2 * (size_t)f], len = a.fgeo[2 * (size_t)f + 1];
+  const int eL = fc.z & 3, eR = (fc.z >> 2) & 3;
+  const double2* fp2 = reinterpret_cast<const double2*>(a.fp);
+  double phi[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const size_t oL = ((size_t)(eL * NQ + k) * a.n_pad + fc.x) * 2;
+    const size_t oR = ((size_t)(eR * NQ + NQ - 1 - k) * a.n_pad + fc.y) * 2;
+    const double2 l0 = fp2[oL], l1 = fp2[oL + 1];
+    const double2 r0 = fp2[oR], r1 = fp2[oR + 1];
+    const double uL[4] = {l0.x, l0.y, l1.x, l1.y};
+    const double uR[4] = {r0.x, r0.y, r1.x, r1.y};
+    double F[4];
+    hll<double>(uL, uR, nrm.x, nrm.y, a.gamma, F);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) phi[c] = phi[c] + FaceRule<NQ>::w[k] * F[c];
+  }
+  double2* out = reinterpret_cast<double2*>(a.phi) + 2 * (size_t)f;
+  out[0] = make_double2(phi[0] * len.x, phi[1] * len.x);
+  out[1] = make_double2(phi[2] * len.x, phi[3] * len.x);
+}
+
+template <int NQ>
+__global__ __launch_bounds__(256) void k_face_flux(FaceFluxArgs a) {
+  const int f = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (f < a.n_face) face_flux<NQ>(a, f);
+}
+
+struct CellUpdateArgs {
+  const int4* __restrict__ cfaces;     // [n_pad]: faces of local edges 0..2, L bits
+  const double* __restrict__ vol;      // [n_pad]
+  const double* __restrict__ phi;      // [n_face][4]
   const double* Un;                    // [n][4]
   const double* Uk;                    // [n][4]
   double* out;                         // R or U^(k+1)
   const double* dt;                    // device scalar
   double ca, cb, cc;                   // out = ca Un + cb Uk + cc (dt R)
-  double gamma;
-  int n_cell, n_pad;
+  int n_cell;
 };
 
-template <int NQ, bool RK>
-__device__ __forceinline__ void flux_cell(const FluxArgs& a, int t) {
-  const int4 nb = a.nbinfo[t];
-  const double* g = a.geo + (size_t)t * 10;
-  const double2* fp2 = reinterpret_cast<const double2*>(a.fp);
+template <bool RK>
+__device__ __forceinline__ void cell_update(const CellUpdateArgs& a, int t) {
+  const int4 cf = a.cfaces[t];
+  const double2* ph = reinterpret_cast<const double2*>(a.phi);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const int j = e == 0 ? nb.x : (e == 1 ? nb.y : nb.z);
-    const int ej = (nb.w >> (2 * e)) & 3;
-    const bool isL = (nb.w >> (6 + e)) & 1;
-    const double nx = g[3 * e], ny = g[3 * e + 1], len = g[3 * e + 2];
-    double phi[4] = {0.0, 0.0, 0.0, 0.0};
+    const size_t f = (size_t)(e == 0 ? cf.x : (e == 1 ? cf.y : cf.z));
+    const bool isL = (cf.w >> e) & 1;
+    const double2 x = ph[2 * f], y = ph[2 * f + 1];
+    const double p[4] = {x.x, x.y, y.x, y.y};
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int qi = e * NQ + (isL ? k : NQ - 1 - k);
-      const int qj = ej * NQ + (isL ? NQ - 1 - k : k);
-      const size_t oi = ((size_t)qi * a.n_pad + t) * 2;
-      const size_t oj = ((size_t)qj * a.n_pad + j) * 2;
-      const double2 i0 = fp2[oi], i1 = fp2[oi + 1];
-      const double2 j0 = fp2[oj], j1 = fp2[oj + 1];
-      const double own[4] = {i0.x, i0.y, i1.x, i1.y};
-      const double oth[4] = {j0.x, j0.y, j1.x, j1.y};
-      double F[4];
-      if (isL) hll<double>(own, oth, nx, ny, a.gamma, F);
-      else hll<double>(oth, own, nx, ny, a.gamma, F);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) phi[c] = phi[c] + FaceRule<NQ>::w[k] * F[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const double p = phi[c] * len;
-      acc[c] = isL ? acc[c] + p : acc[c] - p;
-    }
+    for (int c = 0; c < 4; ++c) acc[c] = isL ? acc[c] + p[c] : acc[c] - p[c];
   }
-  const double ia = -1.0 / g[9];
+  const double ia = -1.0 / a.vol[t];
   double R[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) R[c] = acc[c] * ia;
@@ -609,11 +633,10 @@ __device__ __forceinline__ void flux_cell(const FluxArgs& a, int t) {
   }
 }
 
-template <int NQ, bool RK>
-__global__ __launch_bounds__(256) void k_flux_update(FluxArgs a) {
+template <bool RK>
+__global__ __launch_bounds__(256) void k_cell_update(CellUpdateArgs a) {
   const int t = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (t >= a.n_cell) return;
-  flux_cell<NQ, RK>(a, t);
+  if (t < a.n_cell) cell_update<RK>(a, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -908,7 +931,8 @@ __global__ __launch_bounds__(256) void k_lincomb(double* out, double a1, const d
 // One mesh of a batch: the arguments of its three RK stages.
 struct BatchMeshDev {
   ReconArgs r[3];          // reconstruction input of stage k
-  FluxArgs f[3];           // flux, gather and update of stage k
+  FaceFluxArgs ff;         // face fluxes (the same buffers every stage)
+  CellUpdateArgs cu[3];    // gather and update of stage k
   const double* U;         // cell averages at the start of the step
   const double* geo;
   double* dt;              // this mesh's step (device scalar)
@@ -958,11 +982,31 @@ __global__ __launch_bounds__(256) void k_batch_reconstruct(const BatchMeshDev* _
   }
 }
 
-// Persistent flux + gather + stage update over (mesh, 64-cell chunk) items.
-__global__ __launch_bounds__(256) void k_batch_flux(const BatchMeshDev* __restrict__ meshes,
-                                                    const int2* __restrict__ items,
-                                                    const int* __restrict__ wave_start,
-                                                    int n_waves, int stage_k) {
+// Persistent face fluxes over (mesh, 64-face chunk) items.
+__global__ __launch_bounds__(256) void k_batch_face_flux(const BatchMeshDev* __restrict__ meshes,
+                                                         const int2* __restrict__ items,
+                                                         const int* __restrict__ wave_start,
+                                                         int n_waves) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (w >= n_waves) return;
+  const int i0 = wave_start[w], i1 = wave_start[w + 1];
+  for (int i = i0; i < i1; ++i) {
+    const int2 it = items[i];
+    const int m = __builtin_amdgcn_readfirstlane(it.x);
+    const BatchMeshDev& d = meshes[m];
+    const int f = it.y * 64 + lane;
+    if (f >= d.ff.n_face) continue;
+    if (d.pq % 10 == 2) face_flux<2>(d.ff, f);
+    else face_flux<3>(d.ff, f);
+  }
+}
+
+// Persistent gather + stage update over (mesh, 64-cell chunk) items.
+__global__ __launch_bounds__(256) void k_batch_cell_update(const BatchMeshDev* __restrict__ meshes,
+                                                           const int2* __restrict__ items,
+                                                           const int* __restrict__ wave_start,
+                                                           int n_waves, int stage_k) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (w >= n_waves) return;
@@ -973,8 +1017,7 @@ __global__ __launch_bounds__(256) void k_batch_flux(const BatchMeshDev* __restri
     const BatchMeshDev& d = meshes[m];
     const int t = it.y * 64 + lane;
     if (t >= d.n_cell) continue;
-    if (d.pq % 10 == 2) flux_cell<2, true>(d.f[stage_k], t);
-    else flux_cell<3, true>(d.f[stage_k], t);
+    cell_update<true>(d.cu[stage_k], t);
   }
 }
 

@@ -562,6 +562,41 @@ int mesh_setup(Mesh& m, const teno_params& p) {
     m.geo[(size_t)t * 10 + 9] = m.area[i];
   }
 
+  // ---- face-ordered data for the flux kernels ----
+  {
+    std::vector<int32_t> order(m.nf), rank(m.nf);
+    for (int f = 0; f < m.nf; ++f) order[f] = f;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      const int la = m.inv[m.fL[a]], lb = m.inv[m.fL[b]];
+      return la < lb || (la == lb && m.fLe[a] < m.fLe[b]);
+    });
+    m.face_cells.assign((size_t)m.nf * 4, 0);
+    m.face_geo.assign((size_t)m.nf * 4, 0.0);
+    for (int k = 0; k < m.nf; ++k) {
+      const int f = order[k];
+      rank[f] = k;
+      m.face_cells[(size_t)k * 4 + 0] = m.inv[m.fL[f]];
+      m.face_cells[(size_t)k * 4 + 1] = m.inv[m.fR[f]];
+      m.face_cells[(size_t)k * 4 + 2] = (m.fLe[f] & 3) | ((m.fRe[f] & 3) << 2);
+      m.face_geo[(size_t)k * 4 + 0] = m.fnx[f];
+      m.face_geo[(size_t)k * 4 + 1] = m.fny[f];
+      m.face_geo[(size_t)k * 4 + 2] = m.flen[f];
+    }
+    m.cell_faces.assign((size_t)m.n_pad * 4, 0);
+    m.vol.assign(m.n_pad, 1.0);
+    for (int t = 0; t < nc; ++t) {
+      const int i = m.perm[t];
+      int32_t bits = 0;
+      for (int e = 0; e < 3; ++e) {
+        const int f = m.cface[3 * (size_t)i + e];
+        m.cell_faces[(size_t)t * 4 + e] = rank[f];
+        if (m.fL[f] == i && m.fLe[f] == e) bits |= 1 << e;
+      }
+      m.cell_faces[(size_t)t * 4 + 3] = bits;
+      m.vol[t] = m.area[i];
+    }
+  }
+
   // ---- reverse stencil lists for the adjoint gather ----
   const int R4 = d.rows4 * 4;
   m.rev_ptr.assign(nc + 1, 0);

@@ -73,6 +73,12 @@ struct teno_solver {
   double2* M = nullptr;
   int4* nbinfo = nullptr;
   double* geo = nullptr;
+  int4* fcell = nullptr;    // face-ordered flux data
+  double2* fgeo = nullptr;
+  int4* cfaces = nullptr;
+  double* vol = nullptr;
+  double* phi = nullptr;    // face fluxes of the last stage
+  int n_face = 0;
   int32_t* user_of = nullptr;
   int32_t* rev_ptr = nullptr;
   int32_t* rev_ent = nullptr;
@@ -192,30 +198,36 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
 int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
                 const double* dt, double ca, double cb, double cc, bool rk, hipStream_t st,
                 const double* fp = nullptr) {
-  FluxArgs a;
-  a.fp = fp ? fp : s->fp;
-  a.nbinfo = s->nbinfo;
-  a.geo = s->geo;
-  a.Un = Un;
-  a.Uk = Uk;
-  a.out = out;
-  a.dt = dt;
-  a.ca = ca;
-  a.cb = cb;
-  a.cc = cc;
-  a.gamma = s->prm.gamma;
-  a.n_cell = s->n_cell;
-  a.n_pad = s->n_pad;
-  const int blocks = (s->n_cell + 255) / 256;
+  FaceFluxArgs f;
+  f.fp = fp ? fp : s->fp;
+  f.fcell = s->fcell;
+  f.fgeo = s->fgeo;
+  f.phi = s->phi;
+  f.gamma = s->prm.gamma;
+  f.n_face = s->n_face;
+  f.n_pad = s->n_pad;
+  CellUpdateArgs c;
+  c.cfaces = s->cfaces;
+  c.vol = s->vol;
+  c.phi = s->phi;
+  c.Un = Un;
+  c.Uk = Uk;
+  c.out = out;
+  c.dt = dt;
+  c.ca = ca;
+  c.cb = cb;
+  c.cc = cc;
+  c.n_cell = s->n_cell;
+  const int fblocks = (s->n_face + 255) / 256;
+  const int cblocks = (s->n_cell + 255) / 256;
   int rc = TENO_OK;
   auto go = [&](auto NQ) {
     rc = timed(s, 1, st, [&]() {
+      hipLaunchKernelGGL((k_face_flux<decltype(NQ)::value>), dim3(fblocks), dim3(256), 0, st, f);
       if (rk)
-        hipLaunchKernelGGL((k_flux_update<decltype(NQ)::value, true>), dim3(blocks), dim3(256), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_cell_update<true>), dim3(cblocks), dim3(256), 0, st, c);
       else
-        hipLaunchKernelGGL((k_flux_update<decltype(NQ)::value, false>), dim3(blocks), dim3(256), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_cell_update<false>), dim3(cblocks), dim3(256), 0, st, c);
     });
   };
   if (s->d.nq == 2) go(IC<2>{});
@@ -422,6 +434,12 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
   A(s->idx, m.idx.size() / 4);
   A(s->M, m.M.size() / 2);
   A(s->nbinfo, np);
+  s->n_face = m.nf;
+  A(s->fcell, (size_t)m.nf);
+  A(s->fgeo, (size_t)m.nf * 2);
+  A(s->cfaces, np);
+  A(s->vol, np);
+  A(s->phi, (size_t)m.nf * 4);
   A(s->geo, np * 10);
   A(s->user_of, np);
   A(s->rev_ptr, nc + 1);
@@ -448,6 +466,10 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
   } ups[] = {{s->idx, m.idx.data(), m.idx.size() * sizeof(int32_t)},
              {s->M, m.M.data(), m.M.size() * sizeof(double)},
              {s->nbinfo, m.nbinfo.data(), m.nbinfo.size() * sizeof(int32_t)},
+             {s->fcell, m.face_cells.data(), m.face_cells.size() * sizeof(int32_t)},
+             {s->fgeo, m.face_geo.data(), m.face_geo.size() * sizeof(double)},
+             {s->cfaces, m.cell_faces.data(), m.cell_faces.size() * sizeof(int32_t)},
+             {s->vol, m.vol.data(), m.vol.size() * sizeof(double)},
              {s->geo, m.geo.data(), m.geo.size() * sizeof(double)},
              {s->user_of, m.user_of.data(), m.user_of.size() * sizeof(int32_t)},
              {s->rev_ptr, m.rev_ptr.data(), m.rev_ptr.size() * sizeof(int32_t)},
@@ -675,8 +697,10 @@ struct teno_batch {
   BatchMeshDev* meshes = nullptr;
   int2* items_r = nullptr;     // reconstruction items, all orders
   int* start_r = nullptr;      // wave starts per launch, concatenated
-  int2* items_f = nullptr;
+  int2* items_f = nullptr;     // face items (64-face chunks)
   int* start_f = nullptr;
+  int2* items_c = nullptr;     // cell items (64-cell chunks)
+  int* start_c = nullptr;
   int2* items_dt = nullptr;
   int* start_dt = nullptr;     // per mesh
   double* partial = nullptr;
@@ -685,7 +709,7 @@ struct teno_batch {
     int pq, item0, wave0, n_waves;
   };
   std::vector<RLaunch> rplan;
-  int n_waves_f = 0, n_items_dt = 0;
+  int n_waves_f = 0, n_waves_c = 0, n_items_dt = 0;
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -785,15 +809,20 @@ int batch_plan(teno_batch* b) {
     b->rplan.push_back({pq, item0, (int)starts_all.size(), waves});
     starts_all.insert(starts_all.end(), st.begin(), st.end());
   }
-  // flux items (64-cell chunks) and dt items (256-cell blocks)
-  std::vector<int2> fitems, ditems;
-  std::vector<double> fcost;
+  // face items (64-face chunks), cell items (64-cell chunks) and dt items
+  // (256-cell blocks)
+  std::vector<int2> fitems, citems, ditems;
+  std::vector<double> fcost, ccost;
   std::vector<int> dstart(n + 1, 0);
   for (int m : morder) {
     const teno_solver* s = b->sv[m];
-    for (int u = 0; u < (s->n_cell + 63) / 64; ++u) {
+    for (int u = 0; u < (s->n_face + 63) / 64; ++u) {
       fitems.push_back(make_int2(m, u));
       fcost.push_back((double)s->d.nq);
+    }
+    for (int u = 0; u < (s->n_cell + 63) / 64; ++u) {
+      citems.push_back(make_int2(m, u));
+      ccost.push_back(1.0);
     }
   }
   for (int m = 0; m < n; ++m) {
@@ -801,9 +830,11 @@ int batch_plan(teno_batch* b) {
     for (int u = 0; u < (b->sv[m]->n_cell + 255) / 256; ++u) ditems.push_back(make_int2(m, u));
   }
   dstart[n] = (int)ditems.size();
-  std::vector<int> fstart;
+  std::vector<int> fstart, cstart;
   balanced_starts(fcost, waves, fstart);
+  balanced_starts(ccost, waves, cstart);
   b->n_waves_f = waves;
+  b->n_waves_c = waves;
   b->n_items_dt = (int)ditems.size();
   int rc = TENO_OK;
   auto A = [&](auto& p, size_t c) {
@@ -814,6 +845,8 @@ int batch_plan(teno_batch* b) {
   A(b->start_r, starts_all.size());
   A(b->items_f, fitems.size());
   A(b->start_f, fstart.size());
+  A(b->items_c, citems.size());
+  A(b->start_c, cstart.size());
   A(b->items_dt, ditems.size());
   A(b->start_dt, dstart.size());
   A(b->partial, ditems.size());
@@ -826,6 +859,8 @@ int batch_plan(teno_batch* b) {
              {b->start_r, starts_all.data(), starts_all.size() * sizeof(int)},
              {b->items_f, fitems.data(), fitems.size() * sizeof(int2)},
              {b->start_f, fstart.data(), fstart.size() * sizeof(int)},
+             {b->items_c, citems.data(), citems.size() * sizeof(int2)},
+             {b->start_c, cstart.data(), cstart.size() * sizeof(int)},
              {b->items_dt, ditems.data(), ditems.size() * sizeof(int2)},
              {b->start_dt, dstart.data(), dstart.size() * sizeof(int)}};
   for (auto& u : ups) {
@@ -864,21 +899,27 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
       a.eps = s->prm.eps;
       a.gamma = s->prm.gamma;
       a.tie_rel = s->prm.tie_rel;
-      FluxArgs& f = d.f[k];
-      f.fp = s->fp;
-      f.nbinfo = s->nbinfo;
-      f.geo = s->geo;
-      f.Un = U[m];
-      f.Uk = in[k];
-      f.out = out[k];
-      f.dt = dt ? dt + m : nullptr;
-      f.ca = kStageA[k];
-      f.cb = kStageB[k];
-      f.cc = kStageC[k];
-      f.gamma = s->prm.gamma;
-      f.n_cell = s->n_cell;
-      f.n_pad = s->n_pad;
+      CellUpdateArgs& c = d.cu[k];
+      c.cfaces = s->cfaces;
+      c.vol = s->vol;
+      c.phi = s->phi;
+      c.Un = U[m];
+      c.Uk = in[k];
+      c.out = out[k];
+      c.dt = dt ? dt + m : nullptr;
+      c.ca = kStageA[k];
+      c.cb = kStageB[k];
+      c.cc = kStageC[k];
+      c.n_cell = s->n_cell;
     }
+    FaceFluxArgs& f = d.ff;
+    f.fp = s->fp;
+    f.fcell = s->fcell;
+    f.fgeo = s->fgeo;
+    f.phi = s->phi;
+    f.gamma = s->prm.gamma;
+    f.n_face = s->n_face;
+    f.n_pad = s->n_pad;
     d.U = U[m];
     d.geo = s->geo;
     d.dt = dt ? const_cast<double*>(dt) + m : nullptr;
@@ -920,10 +961,13 @@ void batch_launch_recon(teno_batch* b, int k, hipStream_t st) {
 
 void batch_launch_step(teno_batch* b, hipStream_t st) {
   const int fblocks = (b->n_waves_f + 3) / 4;
+  const int cblocks = (b->n_waves_c + 3) / 4;
   for (int k = 0; k < 3; ++k) {
     batch_launch_recon(b, k, st);
-    hipLaunchKernelGGL(k_batch_flux, dim3(fblocks), dim3(256), 0, st, b->meshes, b->items_f,
-                       b->start_f, b->n_waves_f, k);
+    hipLaunchKernelGGL(k_batch_face_flux, dim3(fblocks), dim3(256), 0, st, b->meshes, b->items_f,
+                       b->start_f, b->n_waves_f);
+    hipLaunchKernelGGL(k_batch_cell_update, dim3(cblocks), dim3(256), 0, st, b->meshes,
+                       b->items_c, b->start_c, b->n_waves_c, k);
   }
 }
 
