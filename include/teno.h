@@ -202,7 +202,8 @@ typedef struct teno_batch_tuning {
   int32_t order_mode;    /* 0: one reconstruction launch per stage for every
                             order (dispatch per work item); 1: one launch per
                             order present, each with that order's registers */
-  int32_t waves_per_cu;  /* persistent wavefronts per compute unit, 1..32     */
+  int32_t waves_per_cu;  /* persistent wavefronts per compute unit, 1..32;   */
+                         /* 0: one wavefront per work item (no persistence)  */
   int32_t item_order;    /* 0: mesh order; 1: largest order first            */
   int32_t use_graph;     /* 1: capture one step as a HIP graph and replay it  */
 } teno_batch_tuning;

@@ -85,7 +85,7 @@ class Batch:
 
 
 CANDIDATES = [dict(order_mode=om, waves_per_cu=w, item_order=io, use_graph=1)
-              for om, w, io in itertools.product((0, 1), (4, 8, 16), (0, 1))]
+              for om, w, io in itertools.product((0, 1), (0, 4, 8, 16), (0, 1))]
 
 
 def autotune(batch: Batch, U, dt, steps: int = 3, cache: str | None = None, verbose=False):

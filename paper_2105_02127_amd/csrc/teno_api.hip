@@ -749,8 +749,16 @@ namespace {
 
 // Splits items [0, n) with costs into `waves` contiguous ranges of nearly
 // equal total cost; writes waves+1 starts.
-void balanced_starts(const std::vector<double>& cost, int waves, std::vector<int>& starts) {
+// Splits items 0..n-1 into `waves` contiguous ranges of about equal cost;
+// waves == 0 gives every item its own wavefront (the hardware then balances
+// the load).  Returns the number of wavefronts.
+int balanced_starts(const std::vector<double>& cost, int waves, std::vector<int>& starts) {
   const int n = (int)cost.size();
+  if (waves == 0) {
+    starts.resize(n + 1);
+    for (int i = 0; i <= n; ++i) starts[i] = i;
+    return n;
+  }
   double total = 0.0;
   for (double c : cost) total += c;
   starts.assign(waves + 1, n);
@@ -763,6 +771,7 @@ void balanced_starts(const std::vector<double>& cost, int waves, std::vector<int
   }
   for (; w < waves; ++w) starts[w] = n;
   starts[waves] = n;
+  return waves;
 }
 
 int batch_plan(teno_batch* b) {
@@ -770,7 +779,7 @@ int batch_plan(teno_batch* b) {
   b->free_plan();
   const int n = b->n;
   const teno_batch_tuning& T = b->tune;
-  const int waves = std::max(1, T.waves_per_cu) * b->n_cu;
+  const int waves = T.waves_per_cu * b->n_cu;  // 0: one wavefront per item
   // mesh order for the work list
   std::vector<int> morder(n);
   for (int m = 0; m < n; ++m) morder[m] = m;
@@ -804,9 +813,9 @@ int batch_plan(teno_batch* b) {
       }
     }
     std::vector<int> st;
-    balanced_starts(cost, waves, st);
+    const int nw = balanced_starts(cost, waves, st);
     for (int& x : st) x += item0;
-    b->rplan.push_back({pq, item0, (int)starts_all.size(), waves});
+    b->rplan.push_back({pq, item0, (int)starts_all.size(), nw});
     starts_all.insert(starts_all.end(), st.begin(), st.end());
   }
   // face items (64-face chunks), cell items (64-cell chunks) and dt items
@@ -831,10 +840,8 @@ int batch_plan(teno_batch* b) {
   }
   dstart[n] = (int)ditems.size();
   std::vector<int> fstart, cstart;
-  balanced_starts(fcost, waves, fstart);
-  balanced_starts(ccost, waves, cstart);
-  b->n_waves_f = waves;
-  b->n_waves_c = waves;
+  b->n_waves_f = balanced_starts(fcost, waves, fstart);
+  b->n_waves_c = balanced_starts(ccost, waves, cstart);
   b->n_items_dt = (int)ditems.size();
   int rc = TENO_OK;
   auto A = [&](auto& p, size_t c) {
@@ -1006,7 +1013,7 @@ int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out) 
 int teno_batch_set_tuning(teno_batch* b, const teno_batch_tuning* t) {
   if (!b || !t) return fail(TENO_EARG, "null argument");
   if (t->order_mode < 0 || t->order_mode > 1 || t->item_order < 0 || t->item_order > 1 ||
-      t->waves_per_cu < 1 || t->waves_per_cu > 32 || t->use_graph < 0 || t->use_graph > 1)
+      t->waves_per_cu < 0 || t->waves_per_cu > 32 || t->use_graph < 0 || t->use_graph > 1)
     return fail(TENO_EARG, "tuning out of range");
   DeviceScope ds(b->device);
   b->tune = *t;

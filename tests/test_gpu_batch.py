@@ -37,6 +37,7 @@ SPECS = [(12, 3, 501), (17, 6, 502), (9, 4, 503), (21, 5, 504), (13, 6, 505), (1
     dict(order_mode=1, waves_per_cu=8, item_order=1, use_graph=0),
     dict(order_mode=0, waves_per_cu=16, item_order=1, use_graph=1),
     dict(order_mode=1, waves_per_cu=1, item_order=0, use_graph=1),
+    dict(order_mode=1, waves_per_cu=0, item_order=1, use_graph=1),
 ])
 def test_batch_step_equals_single_mesh_steps(torch_cuda, tuning):
     torch = torch_cuda
