@@ -854,34 +854,34 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   a.own[(size_t)cell * 4 + v] = gsum - dsum;
 }
 
-// Phase 3 (one lane per cell): U_bar[j] = own[j] + sum over every stencil
-// row naming j of that row's adjoint, in a fixed order (no atomics); then
-// out = U_bar + beta * extra (extra nullable).
+// Phase 3 (four lanes per cell): U_bar[j] = own[j] + the adjoints of every
+// stencil row naming j (reverse list rev_ptr[j] .. rev_ptr[j+1]-1).  Lane q
+// of the cell's quad sums entries q, q+4, ... in list order, fetching its
+// entries and their rows GB at a time (the walk is a chain of dependent
+// loads); the quad then adds its four partial sums in lane order.  Fixed
+// order, no atomics.  Then out = U_bar + beta * extra (extra nullable).
 __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ own,
                                                     const double* __restrict__ dbar,
                                                     const int32_t* __restrict__ rev_ptr,
                                                     const int32_t* __restrict__ rev_ent, int rows4x4,
-                                                    int n_cell, int n_pad, const double* extra,
-                                                    double beta, double* out) {
-  const int j = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+                                                    int n_cell, const double* extra, double beta,
+                                                    double* out) {
+  const int gid = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int j = gid >> 2, q = gid & 3;
+  // whole quads leave together (n_cell cells use 4 * n_cell lanes)
   if (j >= n_cell) return;
-  double s[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) s[c] = own[(size_t)j * 4 + c];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
   const int b = rev_ptr[j], e = rev_ptr[j + 1];
-  // Entries are fetched GB at a time (all list entries, then all rows, each
-  // group in flight together) and then added in list order: the walk is a
-  // chain of dependent loads, so batching sets its length.
-  constexpr int GB = 8;
+  constexpr int GB = 4;
   auto row_of = [&](int ent) {
     const int i = ent / rows4x4, r = ent - i * rows4x4;
     return reinterpret_cast<const double2*>(dbar + dbar_index(i, r, rows4x4));
   };
-  int t = b;
-  for (; t + GB <= e; t += GB) {
+  int t = b + q;
+  for (; t + 4 * (GB - 1) < e; t += 4 * GB) {
     int ent[GB];
 #pragma unroll
-    for (int k = 0; k < GB; ++k) ent[k] = rev_ent[t + k];
+    for (int k = 0; k < GB; ++k) ent[k] = rev_ent[t + 4 * k];
     double2 x[GB], y[GB];
 #pragma unroll
     for (int k = 0; k < GB; ++k) {
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ o
       s[3] += y[k].y;
     }
   }
-  for (; t < e; ++t) {
+  for (; t < e; t += 4) {
     const double2* d2 = row_of(rev_ent[t]);
     const double2 x = d2[0], y = d2[1];
     s[0] += x.x;
@@ -905,12 +905,14 @@ __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ o
     s[2] += y.x;
     s[3] += y.y;
   }
-  if (extra) {
+  double tot[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) s[c] = s[c] + beta * extra[(size_t)j * 4 + c];
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) out[(size_t)j * 4 + c] = s[c];
+  for (int c = 0; c < 4; ++c)
+    tot[c] = ((quad_bcast<0>(s[c]) + quad_bcast<1>(s[c])) + quad_bcast<2>(s[c])) + quad_bcast<3>(s[c]);
+  // lane q finishes variable q
+  double v = own[(size_t)j * 4 + q] + pick4(tot[0], tot[1], tot[2], tot[3], q);
+  if (extra) v = v + beta * extra[(size_t)j * 4 + q];
+  out[(size_t)j * 4 + q] = v;
 }
 
 // out = a1 x1 + a2 x2 (+ a3 x3), elementwise over n doubles.

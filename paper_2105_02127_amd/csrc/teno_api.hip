@@ -276,14 +276,14 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   ra.n_tiles = s->n_tiles;
   ra.n_pad = s->n_pad;
   const int tblocks = (s->n_tiles + 3) / 4;
+  const int qblocks = (int)(((int64_t)s->n_cell * 4 + 255) / 256);
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 3, st, [&]() {
       hipLaunchKernelGGL((k_adj_face<decltype(NQ)::value>), dim3(cblocks), dim3(256), 0, st, fa);
       hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
                          dim3(256), 0, st, ra);
-      hipLaunchKernelGGL(k_adj_gather, dim3(cblocks), dim3(256), 0, st, s->own, s->dbar,
-                         s->rev_ptr, s->rev_ent, s->d.rows4 * 4, s->n_cell, s->n_pad, extra, beta,
-                         out);
+      hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->dbar,
+                         s->rev_ptr, s->rev_ent, s->d.rows4 * 4, s->n_cell, extra, beta, out);
     });
   });
   return rc;
