@@ -68,9 +68,10 @@ def traffic_from_profiles(workload: str):
         return None
 
 
-def cpu_baseline(mesh, U, order, fallback, steps=1):
+def cpu_baseline(mesh, U, order, fallback, steps=1, single=True):
     """The CPU oracle (as it stands) on the same mesh and state: one full
-    SSP-RK3 step over every cell, set-up excluded, all host threads."""
+    SSP-RK3 step over every cell, set-up excluded, all host threads; then
+    (single) one residual evaluation on one thread."""
     import oracle
     threads = oracle.get_threads()
     om = oracle.OracleMesh(mesh.xy, mesh.tri)
@@ -83,11 +84,30 @@ def cpu_baseline(mesh, U, order, fallback, steps=1):
     for _ in range(steps):
         Uc = om.rk_step(Uc, dt)["U"]
     t = time.perf_counter() - t0
-    return {"value": mesh.n_cell * 3 * steps / t, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} full SSP-RK3 step(s) ({3 * steps} stages) over all {mesh.n_cell} cells "
-                      f"of the same mesh and state; oracle set-up ({t_setup:.1f} s) excluded",
-            "seconds": t}
+    out = {"value": mesh.n_cell * 3 * steps / t, "unit": "cell-updates/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{steps} full SSP-RK3 step(s) ({3 * steps} stages) over all {mesh.n_cell} cells "
+                     f"of the same mesh and state; oracle set-up ({t_setup:.1f} s) excluded",
+           "seconds": t}
+    if single:
+        # one host thread, one residual evaluation (one stage) over every cell
+        # of a 128x128x2 mesh of the same kind (the cost per cell does not
+        # depend on the mesh size; the full mesh would take about half a
+        # minute on one thread)
+        from paper_2105_02127_amd import inputs
+        ms = inputs.jittered_periodic_mesh(128, mesh.seed)
+        Us = inputs.random_lines(ms)
+        oms = oracle.OracleMesh(ms.xy, ms.tri)
+        oms.setup(oracle.params(order=order, fallback=fallback))
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oms.residual(Us)
+        t1 = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        out["single_thread"] = {"value": ms.n_cell / t1, "unit": "cell-updates/s", "cores": 1,
+                                "sample": f"one residual evaluation over the {ms.n_cell} cells of a "
+                                          f"128x128x2 mesh of the same kind", "seconds": t1}
+    return out
 
 
 def adjoint_timing(torch, teno, inputs, steps=200, checkpoint_every=20):
@@ -197,6 +217,8 @@ def main():
     ap.add_argument("--fallback", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-single", action="store_true",
+                    help="skip the single-thread oracle timing")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
@@ -309,7 +331,8 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_timing(torch, teno, inputs)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps,
+                                           single=not args.no_cpu_single)
     print(json.dumps(out), flush=True)
 
 
