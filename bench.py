@@ -150,6 +150,47 @@ def adjoint_timing(torch, teno, inputs, steps=200, checkpoint_every=20):
             "note": "backward includes recomputing each 20-step segment from its checkpoint"}
 
 
+# Tab. runtime analysis (Sec. 5.10), KHI on 577,416 triangles, 56 CPU threads:
+# t_norm = reconstruction seconds per iteration per element, as printed.
+PAPER_KHI_T_NORM = {3: 1.32e-6, 4: 1.66e-6, 5: 1.90e-6, 6: 2.20e-6}
+
+
+def khi_timing(torch, teno, inputs, steps=10, warmup=2):
+    """The paper's KHI timing workload (Sec. 5.8, 5.10) at its size: TENO3-6
+    on the 537x537x2 mesh (576,738 cells), per-stage throughput and the
+    reconstruction time per RK3 step per element beside the paper's t_norm
+    (CPU hardware; context only)."""
+    w, mesh, U0 = inputs.make_workload(6)
+    out = {"workload": "kelvin_helmholtz_N537", "n_cell": mesh.n_cell, "steps": steps, "orders": {}}
+    for order in (3, 4, 5, 6):
+        lm = teno.Mesh(mesh.xy, mesh.tri).setup(order=order, fallback=1)
+        sv = teno.Solver(lm)
+        U = torch.as_tensor(U0[lm.perm], device="cuda")
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            sv.max_dt(U, 0.4, dt)
+            sv.rk_step(U, dt)
+        torch.cuda.synchronize()
+        sv.profile_read(reset=True)
+        sv.profile_enable(True, kinds=("reconstruct",))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sv.max_dt(U, 0.4, dt)
+            sv.rk_step(U, dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sv.profile_enable(False)
+        prof = sv.profile_read(reset=True)
+        rec_ms = prof.ms["reconstruct"] / max(1, prof.launches["reconstruct"])
+        out["orders"][order] = {
+            "value": mesh.n_cell * 3 * steps / el, "unit": "cell-updates/s",
+            "ms_per_step": el * 1e3 / steps,
+            "recon_s_per_step_per_element": 3 * rec_ms * 1e-3 / mesh.n_cell,
+            "paper_t_norm_cpu": PAPER_KHI_T_NORM[order]}
+        del sv, lm, U
+    return out
+
+
 def batch_timing(torch, teno, inputs, steps=10):
     """Batched workload: 64 seeded jittered periodic meshes, N ~ U{32..316},
     order ~ U{3..6}, random-line states; one step = per-mesh dt + one
@@ -221,6 +262,7 @@ def main():
                     help="skip the single-thread oracle timing")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-khi", action="store_true", help="skip the KHI TENO3-6 timings")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-launch HIP events (no roofline figures)")
     ap.add_argument("--breakdown-steps", type=int, default=5,
@@ -330,6 +372,8 @@ def main():
         out["adjoint"] = adjoint_timing(torch, teno, inputs)
     if not args.no_batch:
         out["batched"] = batch_timing(torch, teno, inputs)
+    if not args.no_khi:
+        out["khi"] = khi_timing(torch, teno, inputs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps,
                                            single=not args.no_cpu_single)

@@ -22,6 +22,7 @@ Initial states (conservative variables rho, rho*u, rho*v, E; gamma = 1.4):
     p ~ U[0.03, 1.5], sampled at cell centroids wrapped into [0, 1)^2.
   * ``wave_plus_jump``: the smooth wave with p multiplied by a ratio
     ~ U[2, 10] on the positive side of one random line.
+  * ``kelvin_helmholtz``: the paper's single-mode KHI state (Sec. 5.8).
 """
 from __future__ import annotations
 
@@ -167,6 +168,19 @@ def wave_plus_jump(mesh: MeshData, rng: np.random.Generator | None = None) -> np
     return conservative(rho, 1.0, 1.0, p)
 
 
+def kelvin_helmholtz(mesh: MeshData) -> np.ndarray:
+    """The single-mode Kelvin-Helmholtz state of the paper's KHI test on the
+    periodic square [-0.5, 0.5]^2 (the unit torus shifted by -0.5), sampled
+    at cell centroids: (rho, u) = (2, -0.5) for |y| <= 0.25, (1, 0.5)
+    otherwise; v = 0.01 sin(2 pi x); p = 2.5."""
+    x = centroids(mesh, wrap=True) - 0.5
+    inner = np.abs(x[:, 1]) <= 0.25
+    rho = np.where(inner, 2.0, 1.0)
+    u = np.where(inner, -0.5, 0.5)
+    v = 0.01 * np.sin(2.0 * math.pi * x[:, 0])
+    return conservative(rho, u, v, np.full(mesh.n_cell, 2.5))
+
+
 def disc_mask(mesh: MeshData, center, radius: float) -> np.ndarray:
     """Cells whose centroid lies within `radius` of `center` (periodic distance)."""
     x = centroids(mesh, wrap=True)
@@ -177,13 +191,16 @@ def disc_mask(mesh: MeshData, center, radius: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# The five workloads: (order, mesh size, seed, initial state, steps)
+# Named workloads: (order, mesh size, seed, initial state, steps); the batch
+# workload is batch_specs below
 # ---------------------------------------------------------------------------
 WORKLOADS = {
     1: dict(name="teno3_wave_N32", order=3, n=32, seed=1, ic="smooth_wave", steps=10),
     2: dict(name="teno5_lines_N512", order=5, n=512, seed=2, ic="random_lines", steps=100),
     3: dict(name="teno6_wavejump_N1024", order=6, n=1024, seed=3, ic="wave_plus_jump", steps=50),
     4: dict(name="teno4_adjoint_N256", order=4, n=256, seed=4, ic="random_lines", steps=200),
+    # the paper's KHI timing workload at its size (576,738 ~ 577,416 triangles)
+    6: dict(name="teno5_khi_N537", order=5, n=537, seed=6, ic="kelvin_helmholtz", steps=100),
 }
 
 
@@ -194,6 +211,8 @@ def make_state(mesh: MeshData, ic: str) -> np.ndarray:
         return random_lines(mesh)
     if ic == "wave_plus_jump":
         return wave_plus_jump(mesh)
+    if ic == "kelvin_helmholtz":
+        return kelvin_helmholtz(mesh)
     raise ValueError(ic)
 
 

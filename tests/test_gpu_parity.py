@@ -165,10 +165,12 @@ def test_trajectory_smooth_wave_10_steps(teno, oracle_mod, torch_cuda):
         assert_states(c.host_user(Ud), U, what=f"step {step}")
 
 
-@pytest.mark.parametrize("order", [3, 5, 6])
-def test_rk_stages_random_lines(teno, oracle_mod, torch_cuda, order):
+@pytest.mark.parametrize("order,ic", [(3, "random_lines"), (5, "random_lines"),
+                                      (6, "random_lines"), (4, "kelvin_helmholtz"),
+                                      (5, "kelvin_helmholtz")])
+def test_rk_stages(teno, oracle_mod, torch_cuda, order, ic):
     torch = torch_cuda
-    c = Case(teno, oracle_mod, torch, 18, 40 + order, order)
+    c = Case(teno, oracle_mod, torch, 18, 40 + order, order, ic=ic)
     dto = c.om.dt(c.U, 0.4)
     dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
     ref = c.om.rk_step(c.U, dto, want_stages=True)
@@ -354,3 +356,8 @@ def test_full_size_teno5_lines_sampled(teno, oracle_mod, torch_cuda):
 
 def test_full_size_teno6_wavejump_sampled(teno, oracle_mod, torch_cuda):
     _sampled(teno, oracle_mod, torch_cuda, 3, n_sample=64)
+
+
+def test_full_size_teno5_khi_sampled(teno, oracle_mod, torch_cuda):
+    # the paper's KHI state (Sec. 5.8) on 576,738 cells
+    _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=96)
