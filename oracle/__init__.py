@@ -20,7 +20,7 @@ class Params(C.Structure):
     _fields_ = [("order", C.c_int32), ("nq", C.c_int32), ("variant", C.c_int32),
                 ("power", C.c_int32), ("ct", C.c_double), ("eps", C.c_double),
                 ("gamma", C.c_double), ("tie_rel", C.c_double),
-                ("fallback", C.c_int32), ("pad_", C.c_int32)]
+                ("fallback", C.c_int32), ("pad_", C.c_int32), ("dk_prime", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -67,6 +67,7 @@ def lib():
         L.oracle_basis.argtypes = [C.c_int, ip, ip, dp]
         L.oracle_select.argtypes = [C.POINTER(Params), dp, dp, ip]
         L.oracle_hll.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, dp]
+        L.oracle_cweno_weights.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.oracle_reconstruct_cells.argtypes = [vp, dp, C.c_int, ip, dp, up, dp, C.POINTER(Diag)]
         L.oracle_residual.argtypes = [vp, dp, dp, up, C.c_int, dp, C.POINTER(Diag)]
         L.oracle_residual_cells.argtypes = [vp, dp, C.c_int, ip, dp, up]
@@ -105,12 +106,20 @@ def _check(rc):
     return rc
 
 
-def params(order=5, ct=1e-6, eps=1e-12, power=6, gamma=1.4, nq=0, variant=0, tie_rel=1e-10,
-           fallback=0):
+def params(order=5, ct=1e-6, eps=None, power=None, gamma=1.4, nq=0, variant=0, tie_rel=1e-10,
+           fallback=0, dk_prime=1e4):
+    """Scheme parameters.  eps and power default to the paper's values of
+    the variant: 1e-12 and 6 for TENO (Sec. 3.2), 1e-14 and 4 for CWENO
+    (variant 2, Sec. 2.4)."""
+    if eps is None:
+        eps = 1e-14 if variant == 2 else 1e-12
+    if power is None:
+        power = 4 if variant == 2 else 6
     p = Params()
     p.order, p.ct, p.eps, p.power, p.gamma, p.nq, p.variant, p.tie_rel = \
         order, ct, eps, power, gamma, nq, variant, tie_rel
     p.fallback = fallback
+    p.dk_prime = dk_prime
     return p
 
 
@@ -307,6 +316,15 @@ def select(beta, prm: Params):
     ties = C.c_int()
     fl = lib().oracle_select(C.byref(prm), _d(b), _d(chi), C.byref(ties))
     return fl, chi, ties.value
+
+
+def cweno_weights(beta, prm: Params):
+    """(omega, d): nonlinear and linear CWENO weights of the four stencils."""
+    b = _f64(beta)
+    w = np.empty(4)
+    d = np.empty(4)
+    lib().oracle_cweno_weights(C.byref(prm), _d(b), _d(w), _d(d))
+    return w, d
 
 
 def hll(uL, uR, n, gamma=1.4):

@@ -52,7 +52,7 @@ extern "C" {
 typedef struct oracle_params {
   int32_t order;    // 3..6
   int32_t nq;       // face Gauss points, 0 = ceil(order/2)
-  int32_t variant;  // 0 = TENO, 1 = LINEAR (large stencil everywhere)
+  int32_t variant;  // 0 = TENO, 1 = LINEAR (large stencil everywhere), 2 = CWENO
   int32_t power;    // scale-separation exponent (paper: 6)
   double ct;        // cutoff C_T (paper: 1e-6)
   double eps;       // epsilon in gamma_k (paper: 1e-12)
@@ -61,6 +61,7 @@ typedef struct oracle_params {
   int32_t fallback; // 1: a cell with a non-physical face point uses its cell
                     // average on every face (flags 0); 0: paper as stated
   int32_t pad_;
+  double dk_prime;  // CWENO: d_K = 1 - 1/dk_prime (paper: 1e4)
 } oracle_params;
 
 typedef struct oracle_diag {
@@ -589,6 +590,21 @@ Sel select(const double beta[4], const oracle_params& p) {
   return s;
 }
 
+// CWENO weights (Sec. 2.4): linear weights d_K = 1 - 1/d'_K for the large
+// stencil and d_k = (1 - d_K)/K for the K = 3 small ones; alpha_k =
+// d_k / (beta_k + eps)^power, omega_k = alpha_k / sum alpha.  d gets the
+// linear weights.
+void cweno_weights(const double beta[4], const oracle_params& p, double omega[4], double d[4]) {
+  d[3] = 1.0 - 1.0 / p.dk_prime;
+  for (int k = 0; k < 3; ++k) d[k] = (1.0 - d[3]) / 3.0;
+  double alpha[4], sum = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    alpha[k] = d[k] / ipow(beta[k] + p.eps, p.power);
+    sum += alpha[k];
+  }
+  for (int k = 0; k < 4; ++k) omega[k] = alpha[k] / sum;
+}
+
 inline double re(double x) { return x; }
 inline double re(const cplx& x) { return x.real(); }
 
@@ -625,6 +641,35 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
       for (int s = 0; s < S.qr.m; ++s) b[s] = S.vol[s] * (U[4 * S.cells[s] + v] - u0);
       coef[k].assign(S.qr.n, T(0.0));
       qr_solve(S.qr, b.data(), coef[k].data());
+    }
+    if (m.prm.variant == 2) {
+      // CWENO (Sec. 2.4): P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k
+      double beta[4], w[4], d[4];
+      for (int k = 0; k < 4; ++k) {
+        std::vector<double> rc(coef[k].size());
+        for (size_t l = 0; l < rc.size(); ++l) rc[l] = std::real(coef[k][l]);
+        beta[k] = smoothness(k == 3 ? m.big : m.small, rc.data());
+      }
+      if (beta_out) for (int k = 0; k < 4; ++k) beta_out[4 * v + k] = beta[k];
+      cweno_weights(beta, m.prm, w, d);
+      std::vector<T> abar(nb, T(0.0));
+      for (int l = 0; l < nb; ++l) {
+        T opt = coef[3][l];
+        if (l < ns)
+          for (int k = 0; k < 3; ++k) opt -= d[k] * coef[k][l];
+        abar[l] = (w[3] / d[3]) * opt;
+        if (l < ns)
+          for (int k = 0; k < 3; ++k) abar[l] += w[k] * coef[k][l];
+      }
+      for (int e = 0; e < 3; ++e)
+        for (int kq = 0; kq < m.nq; ++kq) {
+          double xi, eta;
+          face_point(e, m.gq_t[kq], xi, eta);
+          T val = u0;
+          for (int l = 0; l < nb; ++l) val += abar[l] * psi(m.big, l, xi, eta);
+          fp[(e * m.nq + kq) * 4 + v] = val;
+        }
+      continue;  // no selection: flags stay 0
     }
     unsigned f4;
     if (frozen) {
@@ -843,6 +888,7 @@ void oracle_default_params(oracle_params* p) {
   p->tie_rel = 1e-10;
   p->fallback = 0;
   p->pad_ = 0;
+  p->dk_prime = 1e4;
 }
 
 // Geometry and faces (Sec. 2.1).  period may be NULL (no periodic wrap).
@@ -970,7 +1016,8 @@ int oracle_mesh_faces(void* h, int* fL, int* fR, int* fLe, int* fRe, double* n, 
 int oracle_setup(void* h, const oracle_params* p, int all) {
   Mesh* m = (Mesh*)h;
   if (p->order < 3 || p->order > 6) return fail("order must be 3..6");
-  if (p->variant != 0 && p->variant != 1) return fail("variant must be 0 or 1");
+  if (p->variant < 0 || p->variant > 2) return fail("variant must be 0, 1 or 2");
+  if (p->variant == 2 && !(p->dk_prime > 1.0)) return fail("CWENO needs dk_prime > 1");
   if (p->ct < 0.0 || p->ct > 1.0 / 3.0) return fail("C_T must lie in [0, 1/K]");
   m->prm = *p;
   m->nq = p->nq > 0 ? p->nq : (p->order + 1) / 2;
@@ -1129,6 +1176,12 @@ int oracle_select(const oracle_params* p, const double* beta, double* chi_out, i
   }
   if (ties) *ties = s.ties;
   return (int)s.flags;
+}
+
+// CWENO weights of one (cell, variable) from its four smoothness indicators
+// (Sec. 2.4); omega [4], d [4] (linear weights).
+void oracle_cweno_weights(const oracle_params* p, const double* beta, double* omega, double* d) {
+  cweno_weights(beta, *p, omega, d);
 }
 
 // HLL flux through unit normal n (Sec. 4).
@@ -1291,6 +1344,7 @@ int oracle_rk_step(void* h, const double* U, double* Uout, double dt, uint16_t* 
 int oracle_jvp(void* h, const double* U, const uint16_t* flags, const double* v, double* Jv) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
+  if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
   const size_t n4 = 4 * (size_t)m->nc;
   const double hh = 1e-30;
   std::vector<cplx> Uc(n4), Rc(n4);
@@ -1305,6 +1359,7 @@ int oracle_jvp(void* h, const double* U, const uint16_t* flags, const double* v,
 int oracle_vjp(void* h, const double* U, const uint16_t* flags, const double* lam, double* Ubar) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
+  if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
   const int nq = m->nq, nc = m->nc;
   const size_t n4 = 4 * (size_t)nc;
   // forward face points with the frozen selection
