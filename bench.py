@@ -152,18 +152,20 @@ def adjoint_timing(torch, teno, inputs, steps=200, checkpoint_every=20):
 
 # Tab. runtime analysis (Sec. 5.10), KHI on 577,416 triangles, 56 CPU threads:
 # t_norm = reconstruction seconds per iteration per element, as printed.
-PAPER_KHI_T_NORM = {3: 1.32e-6, 4: 1.66e-6, 5: 1.90e-6, 6: 2.20e-6}
+PAPER_KHI_T_NORM = {"TENO3": 1.32e-6, "TENO4": 1.66e-6, "TENO5": 1.90e-6, "TENO6": 2.20e-6,
+                    "CWENO5": 1.88e-6, "CWENO6": 2.17e-6}
 
 
 def khi_timing(torch, teno, inputs, steps=10, warmup=2):
     """The paper's KHI timing workload (Sec. 5.8, 5.10) at its size: TENO3-6
-    on the 537x537x2 mesh (576,738 cells), per-stage throughput and the
-    reconstruction time per RK3 step per element beside the paper's t_norm
-    (CPU hardware; context only)."""
+    and CWENO5-6 on the 537x537x2 mesh (576,738 cells), per-stage throughput
+    and the reconstruction time per RK3 step per element beside the paper's
+    t_norm (CPU hardware; context only)."""
     w, mesh, U0 = inputs.make_workload(6)
-    out = {"workload": "kelvin_helmholtz_N537", "n_cell": mesh.n_cell, "steps": steps, "orders": {}}
-    for order in (3, 4, 5, 6):
-        lm = teno.Mesh(mesh.xy, mesh.tri).setup(order=order, fallback=1)
+    out = {"workload": "kelvin_helmholtz_N537", "n_cell": mesh.n_cell, "steps": steps, "schemes": {}}
+    for name, order, variant in (("TENO3", 3, 0), ("TENO4", 4, 0), ("TENO5", 5, 0), ("TENO6", 6, 0),
+                                 ("CWENO5", 5, 2), ("CWENO6", 6, 2)):
+        lm = teno.Mesh(mesh.xy, mesh.tri).setup(order=order, fallback=1, variant=variant)
         sv = teno.Solver(lm)
         U = torch.as_tensor(U0[lm.perm], device="cuda")
         dt = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -182,11 +184,11 @@ def khi_timing(torch, teno, inputs, steps=10, warmup=2):
         sv.profile_enable(False)
         prof = sv.profile_read(reset=True)
         rec_ms = prof.ms["reconstruct"] / max(1, prof.launches["reconstruct"])
-        out["orders"][order] = {
+        out["schemes"][name] = {
             "value": mesh.n_cell * 3 * steps / el, "unit": "cell-updates/s",
             "ms_per_step": el * 1e3 / steps,
             "recon_s_per_step_per_element": 3 * rec_ms * 1e-3 / mesh.n_cell,
-            "paper_t_norm_cpu": PAPER_KHI_T_NORM[order]}
+            "paper_t_norm_cpu": PAPER_KHI_T_NORM[name]}
         del sv, lm, U
     return out
 

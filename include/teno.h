@@ -43,14 +43,18 @@ typedef struct teno_batch teno_batch;
 
 /* Scheme parameters.  Defaults (teno_default_params) are the paper's fixed
  * built-in values: C_T = 1e-6 in both selection steps and eps = 1e-12 with
- * exponent 6 in the scale separation (Sec. 3.2-3.3), gamma = 1.4. */
+ * exponent 6 in the scale separation (Sec. 3.2-3.3), gamma = 1.4.  For the
+ * CWENO variant the paper uses power = 4, eps = 1e-14 and dk_prime = 1e4
+ * (Sec. 2.4). */
 typedef struct teno_params {
   int32_t order;     /* 3..6: large-stencil degree order-1, Sec. 2.2 eq. 03   */
   int32_t n_quad;    /* Gauss points per face, 0 = ceil(order/2)              */
-  int32_t variant;   /* 0 = TENO (Sec. 3), 1 = LINEAR (large stencil only)    */
-  int32_t power;     /* scale-separation exponent (paper: 6)                  */
+  int32_t variant;   /* 0 = TENO (Sec. 3), 1 = LINEAR (large stencil only),   */
+                     /* 2 = CWENO (Sec. 2.4; no selection, flags 0, no        */
+                     /* frozen or adjoint calls, no batches)                  */
+  int32_t power;     /* exponent of the weights (paper: 6 TENO, 4 CWENO)      */
   double ct;         /* cutoff C_T in [0, 1/3] (paper: 1e-6)                  */
-  double eps;        /* epsilon of the scale separation (paper: 1e-12)        */
+  double eps;        /* epsilon of the weights (paper: 1e-12 TENO, 1e-14 CWENO) */
   double gamma;      /* ratio of specific heats                               */
   double tie_rel;    /* near-tie band: |chi/C_T - 1| <= tie_rel is counted    */
   int32_t fallback;  /* 1: a cell with a non-physical face state uses its    */
@@ -59,6 +63,7 @@ typedef struct teno_params {
   int32_t reorder;   /* 1 = Morton order of cells (default), 0 = user order   */
   int32_t n_threads; /* host threads for set-up, 0 = hardware concurrency     */
   int32_t reserved;
+  double dk_prime;   /* CWENO: d_K = 1 - 1/dk_prime > 0 (paper: 1e4)          */
 } teno_params;
 
 typedef struct teno_info {

@@ -206,6 +206,7 @@ struct ReconArgs {
   int n_cell, n_tiles, n_pad;
   int frozen, variant, fallback, power;
   double ct, eps, gamma, tie_rel;
+  double cw_dK, cw_ds;                 // CWENO linear weights: large, each small
 };
 
 __device__ __forceinline__ double gamma_k(double beta, double eps, int power) {
@@ -384,8 +385,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kMaxStage = OrderT<6>::ROWS4 * kTile;
 
 // Reconstruction of one tile of kTile cells by one wavefront; `stage` is
-// this wavefront's LDS area (at least ROWS4 * kTile int4).
-template <int P, int NQ>
+// this wavefront's LDS area (at least ROWS4 * kTile int4).  CW selects the
+// CWENO weighting (Sec. 2.4) instead of the TENO selection (Sec. 3).
+template <int P, int NQ, bool CW = false>
 __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, int lane,
                                                  int4* stage) {
   using O = OrderT<P>;
@@ -454,7 +456,7 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
     nsm = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
   }
   double asm_[5];
-  {
+  if constexpr (!CW) {
     const int cnt = (int)(nsm & 1u) + (int)((nsm >> 1) & 1u) + (int)((nsm >> 2) & 1u);
 #pragma unroll
     for (int l = 0; l < 5; ++l) {
@@ -463,6 +465,21 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
       if (nsm & 2u) acc += as[1][l];
       if (nsm & 4u) acc += as[2][l];
       asm_[l] = cnt > 0 ? acc / (double)cnt : 0.0;
+    }
+  }
+  // CWENO: alpha_k = d_k / (beta_k + eps)^power of the small stencils, with
+  // asm_ = sum_k alpha_k a^k and dsm = sum_k d_k a^k (their shares of the
+  // combination, finished once the large stencil's weight is known)
+  double dsm[CW ? 5 : 1];
+  if constexpr (CW) {
+    const double w0 = a.cw_ds * gamma_k(quad_form(SmoothForm<2>::B.v, as[0]), a.eps, a.power);
+    const double w1 = a.cw_ds * gamma_k(quad_form(SmoothForm<2>::B.v, as[1]), a.eps, a.power);
+    const double w2 = a.cw_ds * gamma_k(quad_form(SmoothForm<2>::B.v, as[2]), a.eps, a.power);
+    ssum = (w0 + w1) + w2;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      asm_[l] = (w0 * as[0][l] + w1 * as[1][l]) + w2 * as[2][l];
+      dsm[l] = a.cw_ds * ((as[0][l] + as[1][l]) + as[2][l]);
     }
   }
 
@@ -475,7 +492,15 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   }
   bool keepK = true;
   int ties = 0;
-  if (frozen) {
+  if constexpr (CW) {
+    // P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k, w = alpha / sum alpha
+    const double wK = a.cw_dK * gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
+    const double iS = 1.0 / (ssum + wK);
+    const double cK = wK / a.cw_dK;
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+      aK[l] = l < 5 ? (cK * (aK[l] - dsm[l]) + asm_[l]) * iS : (cK * aK[l]) * iS;
+  } else if (frozen) {
     keepK = (nib_in & 8u) != 0;
   } else if (a.variant == 0) {
     const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
@@ -484,7 +509,7 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
     keepK = chiK >= a.ct;
     if (!keepK) ties += ties_small;
   }
-  unsigned nib = keepK ? 8u : nsm;
+  unsigned nib = CW ? 0u : (keepK ? 8u : nsm);
   double ab[NU];
 #pragma unroll
   for (int l = 0; l < NU; ++l) ab[l] = keepK ? aK[l] : (l < 5 ? asm_[l] : 0.0);
@@ -531,13 +556,13 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   }
 }
 
-template <int P, int NQ>
+template <int P, int NQ, bool CW>
 __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a) {
   __shared__ int4 stage[4][OrderT<P>::ROWS4 * kTile];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
-  reconstruct_tile<P, NQ>(a, tile, lane, stage[wave]);
+  reconstruct_tile<P, NQ, CW>(a, tile, lane, stage[wave]);
 }
 
 // ---------------------------------------------------------------------------

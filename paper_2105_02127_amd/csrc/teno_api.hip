@@ -184,12 +184,19 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   a.eps = s->prm.eps;
   a.gamma = s->prm.gamma;
   a.tie_rel = s->prm.tie_rel;
+  a.cw_dK = 1.0 - 1.0 / s->prm.dk_prime;
+  a.cw_ds = (1.0 - a.cw_dK) / 3.0;
   const int blocks = (s->n_tiles + 3) / 4;
+  const bool cw = s->prm.variant == 2;
   int rc = TENO_OK;
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 0, st, [&]() {
-      hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value>), dim3(blocks),
-                         dim3(256), 0, st, a);
+      if (cw)
+        hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value, true>),
+                           dim3(blocks), dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value, false>),
+                           dim3(blocks), dim3(256), 0, st, a);
     });
   });
   return rc;
@@ -303,6 +310,13 @@ int check_solver(teno_solver* s) {
   return TENO_OK;
 }
 
+// CWENO (variant 2) has no selection to freeze and hence no adjoint.
+int needs_selection(const teno_solver* s, const char* what) {
+  if (s->prm.variant == 2)
+    return fail(TENO_EARG, std::string(what) + " needs a stencil selection (TENO or LINEAR), not CWENO");
+  return TENO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -323,6 +337,7 @@ void teno_default_params(teno_params* p) {
   p->fallback = 0;
   p->reorder = 1;
   p->n_threads = 0;
+  p->dk_prime = 1e4;
 }
 
 int teno_mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
@@ -528,6 +543,7 @@ int teno_residual(teno_solver* s, const double* U, double* R, uint16_t* flags, v
 int teno_residual_frozen(teno_solver* s, const double* U, double* R, const uint16_t* flags,
                          void* stream) {
   if (int rc = check_solver(s)) return rc;
+  if (int rc = needs_selection(s, "residual_frozen")) return rc;
   if (!U || !R || !flags) return fail(TENO_EARG, "null argument");
   DeviceScope ds(s->device);
   hipStream_t st = (hipStream_t)stream;
@@ -559,6 +575,8 @@ int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk,
   if (k < 0 || k > 2) return fail(TENO_EARG, "stage must be 0, 1 or 2");
   if (!Un || !Uk || !Uk1 || !dt_dev) return fail(TENO_EARG, "null argument");
   if (frozen && !flags) return fail(TENO_EARG, "frozen selection needs flags");
+  if (frozen)
+    if (int rc = needs_selection(s, "a frozen stage")) return rc;
   if (k == 0 && Uk != Un) return fail(TENO_EARG, "stage 0 needs Uk == Un");
   if (Uk1 == Uk && Uk != Un) return fail(TENO_EARG, "Uk1 must not alias Uk");
   DeviceScope ds(s->device);
@@ -570,6 +588,8 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
   if (int rc = check_solver(s)) return rc;
   if (!U || !dt_dev) return fail(TENO_EARG, "null argument");
   if (frozen && !flags3) return fail(TENO_EARG, "frozen selection needs flags3");
+  if (frozen)
+    if (int rc = needs_selection(s, "a frozen step")) return rc;
   DeviceScope ds(s->device);
   hipStream_t st = (hipStream_t)stream;
   const size_t n = (size_t)s->n_cell;
@@ -599,6 +619,7 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
 int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
                       double* U_bar, void* stream) {
   if (int rc = check_solver(s)) return rc;
+  if (int rc = needs_selection(s, "vjp_residual")) return rc;
   if (!U || !flags || !lam || !U_bar) return fail(TENO_EARG, "null argument");
   if (U_bar == lam) return fail(TENO_EARG, "U_bar must not alias lam");
   DeviceScope ds(s->device);
@@ -609,6 +630,7 @@ int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags
                      const double* face_states3, const double* dt_dev, const double* lam_out,
                      double* lam_in, void* stream) {
   if (int rc = check_solver(s)) return rc;
+  if (int rc = needs_selection(s, "vjp_rk_step")) return rc;
   if (!stages || !flags3 || !dt_dev || !lam_out || !lam_in) return fail(TENO_EARG, "null argument");
   DeviceScope ds(s->device);
   hipStream_t st = (hipStream_t)stream;
@@ -990,6 +1012,7 @@ int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out) 
     if (solvers[m]->device != solvers[0]->device) return fail(TENO_EARG, "batch solvers must share a device");
     for (int k = 0; k < m; ++k)
       if (solvers[k] == solvers[m]) return fail(TENO_EARG, "a solver appears twice in the batch");
+    if (solvers[m]->prm.variant == 2) return fail(TENO_EARG, "CWENO meshes cannot be batched");
   }
   DeviceScope ds(solvers[0]->device);
   teno_batch* b = new (std::nothrow) teno_batch();

@@ -22,7 +22,8 @@ class Params(C.Structure):
     _fields_ = [("order", C.c_int32), ("n_quad", C.c_int32), ("variant", C.c_int32),
                 ("power", C.c_int32), ("ct", C.c_double), ("eps", C.c_double),
                 ("gamma", C.c_double), ("tie_rel", C.c_double), ("fallback", C.c_int32),
-                ("reorder", C.c_int32), ("n_threads", C.c_int32), ("reserved", C.c_int32)]
+                ("reorder", C.c_int32), ("n_threads", C.c_int32), ("reserved", C.c_int32),
+                ("dk_prime", C.c_double)]
 
 
 class Info(C.Structure):
@@ -111,8 +112,14 @@ def _check(rc):
 
 
 def default_params(**kw) -> Params:
+    """The library's defaults with `kw` applied.  For the CWENO variant
+    (variant=2) power and eps default to the paper's CWENO values, 4 and
+    1e-14 (Sec. 2.4)."""
     p = Params()
     load().teno_default_params(C.byref(p))
+    if kw.get("variant") == 2:
+        kw.setdefault("power", 4)
+        kw.setdefault("eps", 1e-14)
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError(f"unknown parameter {k}")

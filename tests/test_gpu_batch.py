@@ -91,3 +91,12 @@ def test_autotune_picks_a_valid_schedule(torch_cuda, tmp_path):
     assert best in CANDIDATES and len(timings) == len(CANDIDATES)
     best2, t2 = autotune(b, U, dt, cache=cache)      # served from the cache
     assert best2 == best and t2 == {}
+
+
+def test_cweno_meshes_are_not_batched(torch_cuda):
+    from paper_2105_02127_amd import teno
+    from paper_2105_02127_amd.batch import Batch
+    m = inputs.jittered_periodic_mesh(12, 507)
+    s = teno.Solver(teno.Mesh(m.xy, m.tri).setup(order=4, variant=2))
+    with pytest.raises(teno.TenoError):
+        Batch([s])

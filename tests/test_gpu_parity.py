@@ -129,6 +129,36 @@ def test_reconstruction_and_residual(teno, oracle_mod, torch_cuda, order, n, see
     assert d["first_bad_cell"] == od["first_bad_cell"]
 
 
+@pytest.mark.parametrize("order,ic", [(3, "random_lines"), (5, "random_lines"),
+                                      (6, "wave_plus_jump"), (5, "kelvin_helmholtz")])
+def test_cweno_matches_oracle(teno, oracle_mod, torch_cuda, order, ic):
+    # CWENO weighting (Sec. 2.4): face states, residual and an RK step
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 17, 70 + order, order, ic=ic, variant=2)
+    ores = c.om.residual(c.U, want_fp=True)
+    flags = c.sv.empty_flags()
+    fs = c.sv.reconstruct(c.Ud, flags=flags)
+    R = c.sv.residual(c.Ud)
+    torch.cuda.synchronize()
+    fs_user = np.empty((c.m.n_cell, fs.shape[0], 4))
+    fs_user[c.perm] = fs.permute(1, 0, 2).cpu().numpy()
+    assert_states(fs_user, ores["fp"].reshape(c.m.n_cell, -1, 4), what="CWENO face states")
+    assert (c.flags_user(flags) == 0).all() and (ores["flags"] == 0).all()
+    assert np.abs(c.host_user(R) - ores["R"]).max() <= REL * c.flux_scale()
+    dto = c.om.dt(c.U, 0.4)
+    dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
+    ref = c.om.rk_step(c.U, dto)
+    Ud = c.Ud.clone()
+    c.sv.rk_step(Ud, dt)
+    torch.cuda.synchronize()
+    assert_states(c.host_user(Ud), ref["U"], what="CWENO U^{n+1}")
+    # no selection to freeze: frozen and adjoint calls are refused
+    with pytest.raises(teno.TenoError):
+        c.sv.vjp_residual(c.Ud, flags, c.Ud)
+    with pytest.raises(teno.TenoError):
+        c.sv.residual_frozen(c.Ud, flags)
+
+
 def test_smooth_wave_all_large_stencil(teno, oracle_mod, torch_cuda):
     w = inputs.WORKLOADS[1]
     c = Case(teno, oracle_mod, torch_cuda, w["n"], w["seed"], w["order"], ic="smooth_wave",

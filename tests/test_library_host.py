@@ -3,6 +3,7 @@ oracle (stencil lists exactly, least-squares operators to round-off), error
 paths of mesh creation and set-up."""
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -34,11 +35,35 @@ def test_every_declared_symbol_is_exported(teno):
     assert set(names) == set(teno.SIGNATURES), set(names) ^ set(teno.SIGNATURES)
 
 
-def test_params_struct_layout_matches_header(teno):
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and field offsets of a struct of include/teno.h, from a C compiler."""
+    src = tmp_path / f"{struct}.c"
+    body = "".join(f'  printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "teno.h"\n'
+                   f'int main(void) {{\n  printf("%zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / struct
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("struct,cls", [("teno_params", "Params"), ("teno_info", "Info"),
+                                        ("teno_diag", "Diag"), ("teno_batch_tuning", "BatchTuning")])
+def test_struct_layouts_match_header(teno, tmp_path, struct, cls):
     import ctypes as C
-    assert C.sizeof(teno.Params) == 4 * 4 + 4 * 8 + 4 * 4
+    py = getattr(teno, cls)
+    fields = [f for f, _ in py._fields_]
+    size, offsets = _c_layout(struct, fields, tmp_path)
+    assert C.sizeof(py) == size
+    assert [getattr(py, f).offset for f in fields] == offsets
+
+
+def test_default_params(teno):
     p = teno.default_params()
-    assert (p.order, p.power, p.ct, p.eps, p.gamma, p.fallback, p.reorder) == (5, 6, 1e-6, 1e-12, 1.4, 0, 1)
+    assert (p.order, p.power, p.ct, p.eps, p.gamma, p.fallback, p.reorder, p.dk_prime) == \
+        (5, 6, 1e-6, 1e-12, 1.4, 0, 1, 1e4)
+    c = teno.default_params(variant=2)                  # the paper's CWENO values
+    assert (c.power, c.eps, c.dk_prime) == (4, 1e-14, 1e4)
 
 
 @pytest.mark.parametrize("n,order,seed", [(12, 3, 1), (12, 4, 2), (14, 5, 3), (16, 6, 4)])
