@@ -103,9 +103,11 @@ int teno_mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int
  * three directional third-order stencils of 12 cells), reference-space
  * least-squares matrices and their Householder pseudo-inverses
  * (Sec. 2.2 eqs. 02-10), cell reordering and device packing.
- * Errors: TENO_ESTENCIL, TENO_ERANK, TENO_EARG (bad parameters, or a mesh
- * with n_cell * 4 ceil(rows / 4) >= 2^31 stencil rows, about 28 million
- * cells at order 6). */
+ * Errors: TENO_ESTENCIL (also when a tile of 16 consecutive cells of the
+ * internal order has more than 384 distinct stencil members, which the
+ * default reordering keeps far below), TENO_ERANK, TENO_EARG (bad
+ * parameters, or a mesh with n_cell * 4 ceil(rows / 4) >= 2^31 stencil rows,
+ * about 28 million cells at order 6). */
 int teno_mesh_setup(teno_mesh* m, const teno_params* p);
 
 int teno_mesh_info(const teno_mesh* m, teno_info* out);

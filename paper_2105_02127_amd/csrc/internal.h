@@ -35,6 +35,10 @@ struct Dims {
 
 Dims dims_for(int order, int nq_req);
 
+// Largest number of distinct stencil members a 16-cell tile may have (their
+// states are staged in LDS, 32 bytes each).
+constexpr int kMaxTileMembers = 384;
+
 constexpr int kSmallRows = 11;
 constexpr int kSmallCoef = 5;
 
@@ -62,7 +66,12 @@ struct Mesh {
 
   // ---- packed device images, internal order, tile-major ----
   int n_pad = 0, n_tiles = 0;
-  std::vector<int32_t> idx;     // [n_tiles][rows4][16][4] stencil members (internal)
+  std::vector<int32_t> idx;     // [n_tiles][rows4][16][4] stencil members (internal; host)
+  // distinct stencil members of each tile, staged in LDS by the kernel
+  int ustride = 0;              // list length per tile (largest count, rounded up)
+  std::vector<int32_t> tmem;    // [n_tiles][ustride] sorted, padded with the last
+  std::vector<uint16_t> slot;   // [n_tiles][rows4][16][4] position of each member in its
+                                // tile's list (packed like idx)
   std::vector<double> M;        // [n_tiles][Jp/2][kTile][2] operator entries (pairs)
   std::vector<int32_t> nbinfo;  // [n_pad][4]: 3 neighbours + packed edge/side bits
   std::vector<double> geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area

@@ -197,7 +197,10 @@ __device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, dou
 // ---------------------------------------------------------------------------
 struct ReconArgs {
   const double* __restrict__ U;        // [n_cell][4]
-  const int4* __restrict__ idx;        // [n_tiles][rows4][16] int4
+  const int4* __restrict__ slot;       // [n_tiles][rows4][16][4] uint16, 8 per int4
+  const int* __restrict__ tmem;        // [n_tiles][ustride] distinct members of a tile
+  int ustride;                         // members per tile list
+  int lds_stride;                      // LDS per wavefront in int4 (stage_int4)
   const double2* __restrict__ M;       // [n_tiles][JP/2][kTile] entry pairs
   double* __restrict__ fp;             // [3 nq][n_pad][4]
   uint16_t* flags;                     // out, or in when frozen
@@ -260,8 +263,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 // acc[t][k][v].  Every entry is loaded by exactly one lane, and every
 // coefficient adds the rows one at a time in row order, as a plain GEMV does.
 //
-// Member indices come from LDS (staged once per tile), so a gather waits only
-// on the LDS counter.  NB row buffers live in fixed registers and the row
+// The states of the tile's distinct stencil members and each row's slot among
+// them are staged in LDS once per tile, so the row loop's only memory loads
+// are the operator entries.  NB row buffers live in fixed registers and the row
 // loop is unrolled by NB: while one row is accumulated the next NB-1 are in
 // flight, and no register changes role between iterations (a rotating
 // buffer would force a full wait every row).  prime() issues the first
@@ -282,8 +286,8 @@ struct RowStream {
   static_assert(RS % 2 == 0 && J0 % 2 == 0, "rows are whole pairs");
   using Acc = double[NT][2][4];
 
-  const double* __restrict__ U;
-  const int* sidx;
+  const double* us;                    // LDS: states of the tile's distinct members
+  const uint16_t* sidx;                // LDS: each stencil row's member slot
   const double2* __restrict__ mp;
   int c, g;
   double u0g;
@@ -294,7 +298,7 @@ struct RowStream {
     s = s < NR ? s : NR - 1;  // loads past the last row re-read it (never used)
     const int r = R0 + s;
     const int id = sidx[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
-    x = U[(size_t)id * 4 + (g & 3)];
+    x = us[id * 4 + (g & 3)];
     const double2* __restrict__ mr = mp + (size_t)((J0 + s * RS) / 2) * kTile;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -381,11 +385,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Largest per-wavefront LDS staging area (order 6).
-constexpr int kMaxStage = OrderT<6>::ROWS4 * kTile;
+// LDS of one wavefront, in int4: the tile's member slots (uint16, 8 per
+// int4), then the states of its distinct members (two int4 each).
+__host__ __device__ constexpr int slot_int4(int rows4) { return rows4 * kTile / 2; }
+__host__ __device__ constexpr int stage_int4(int rows4, int ustride) {
+  return slot_int4(rows4) + 2 * ustride;
+}
 
 // Reconstruction of one tile of kTile cells by one wavefront; `stage` is
-// this wavefront's LDS area (at least ROWS4 * kTile int4).  CW selects the
+// this wavefront's LDS area (stage_int4(ROWS4, a.ustride) int4).  CW selects the
 // CWENO weighting (Sec. 2.4) instead of the TENO selection (Sec. 3).
 template <int P, int NQ, bool CW = false>
 __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, int lane,
@@ -393,14 +401,24 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
-  // stage this tile's stencil member indices in LDS ([row4][cell][4] ints)
+  // stage this tile's member slots ([row4][cell][4] uint16) and the states
+  // of its distinct stencil members in LDS
   wave_lds_sync();  // earlier readers of `stage` are done
   {
-    const int4* __restrict__ src = a.idx + (size_t)tile * O::ROWS4 * kTile;
-    for (int i = lane; i < O::ROWS4 * kTile; i += 64) stage[i] = src[i];
+    constexpr int NS = slot_int4(O::ROWS4);
+    const int4* __restrict__ src = a.slot + (size_t)tile * NS;
+    for (int i = lane; i < NS; i += 64) stage[i] = src[i];
+    double2* ust = reinterpret_cast<double2*>(stage + NS);
+    const int* __restrict__ mem = a.tmem + (size_t)tile * a.ustride;
+    for (int i = lane; i < a.ustride; i += 64) {
+      const double2* u = reinterpret_cast<const double2*>(a.U + (size_t)mem[i] * 4);
+      ust[2 * i] = u[0];
+      ust[2 * i + 1] = u[1];
+    }
   }
   wave_lds_sync();
-  const int* sidx = reinterpret_cast<const int*>(stage);
+  const uint16_t* sidx = reinterpret_cast<const uint16_t*>(stage);
+  const double* us = reinterpret_cast<const double*>(stage + slot_int4(O::ROWS4));
   // g: coefficient group of the lane within its cell; v = g % 4: the
   // variable it gathers and, in the selection phase, the variable it owns
   // (with 8 lanes per cell, lanes 4..7 repeat 0..3 and do not write).
@@ -418,15 +436,15 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   //      previous stencil's coefficients are gathered, and the large
   //      stencil's first rows load during that last step ----
   using LargeS = RowStream<33, O::NL, 3 * O::SBLK, stored_row(O::NU)>;
-  LargeS ls{a.U, sidx, mp, c, g, u0};
+  LargeS ls{us, sidx, mp, c, g, u0};
   double as[3][5];
   {
     using S0 = RowStream<0, 11, 0, stored_row(5)>;
     using S1 = RowStream<11, 11, O::SBLK, stored_row(5)>;
     using S2 = RowStream<22, 11, 2 * O::SBLK, stored_row(5)>;
-    S0 s0{a.U, sidx, mp, c, g, u0};
-    S1 s1{a.U, sidx, mp, c, g, u0};
-    S2 s2{a.U, sidx, mp, c, g, u0};
+    S0 s0{us, sidx, mp, c, g, u0};
+    S1 s1{us, sidx, mp, c, g, u0};
+    S2 s2{us, sidx, mp, c, g, u0};
     typename S0::Acc sk0 = {}, sk1 = {}, sk2 = {};
     s0.prime();
     s0.run(sk0);
@@ -558,11 +576,11 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
 
 template <int P, int NQ, bool CW>
 __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a) {
-  __shared__ int4 stage[4][OrderT<P>::ROWS4 * kTile];
+  extern __shared__ int4 lds[];  // 4 wavefronts x a.lds_stride
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
-  reconstruct_tile<P, NQ, CW>(a, tile, lane, stage[wave]);
+  reconstruct_tile<P, NQ, CW>(a, tile, lane, lds + wave * a.lds_stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -994,8 +1012,9 @@ template <int PQ>
 __global__ __launch_bounds__(256) void k_batch_reconstruct(const BatchMeshDev* __restrict__ meshes,
                                                            const int2* __restrict__ items,
                                                            const int* __restrict__ wave_start,
-                                                           int n_waves, int stage_k) {
-  __shared__ int4 stage[4][kMaxStage];
+                                                           int n_waves, int stage_k,
+                                                           int lds_stride) {
+  extern __shared__ int4 lds[];  // 4 wavefronts x lds_stride (the largest mesh's)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (w >= n_waves) return;
@@ -1005,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_batch_reconstruct(const BatchMeshDev* _
     const int m = __builtin_amdgcn_readfirstlane(it.x);
     const int tile = __builtin_amdgcn_readfirstlane(it.y);
     const BatchMeshDev& d = meshes[m];
-    batch_tile<PQ>(d.pq, d.r[stage_k], tile, lane, stage[wave]);
+    batch_tile<PQ>(d.pq, d.r[stage_k], tile, lane, lds + wave * lds_stride);
   }
 }
 

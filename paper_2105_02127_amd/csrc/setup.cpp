@@ -598,6 +598,46 @@ int mesh_setup(Mesh& m, const teno_params& p) {
     }
   }
 
+  // ---- distinct stencil members per tile and their LDS slots ----
+  {
+    std::vector<std::vector<int32_t>> lists(m.n_tiles);
+    std::atomic<int> umax{1};
+    m.slot.assign(m.idx.size(), 0);
+    parallel_for(m.n_tiles, p.n_threads, [&](int tile) {
+      std::vector<int32_t>& u = lists[tile];
+      for (int c = 0; c < kTile; ++c) {
+        const int t = tile * kTile + c;
+        if (t >= nc) break;
+        for (int r = 0; r < d.rows; ++r) u.push_back(m.idx[packed_idx_index(m, t, r)]);
+      }
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      int cur = umax.load();
+      while ((int)u.size() > cur && !umax.compare_exchange_weak(cur, (int)u.size())) {
+      }
+      for (int c = 0; c < kTile; ++c) {
+        const int t = tile * kTile + c;
+        if (t >= nc) break;
+        for (int r = 0; r < d.rows; ++r) {
+          const int64_t k = packed_idx_index(m, t, r);
+          m.slot[k] = (uint16_t)(std::lower_bound(u.begin(), u.end(), m.idx[k]) - u.begin());
+        }
+      }
+    });
+    if (umax.load() > kMaxTileMembers)
+      return fail(TENO_ESTENCIL, "a 16-cell tile has " + std::to_string(umax.load()) +
+                                     " distinct stencil members (limit " +
+                                     std::to_string(kMaxTileMembers) +
+                                     "); keep the default cell reordering");
+    m.ustride = (umax.load() + 15) / 16 * 16;
+    m.tmem.assign((size_t)m.n_tiles * m.ustride, 0);
+    for (int tile = 0; tile < m.n_tiles; ++tile) {
+      const auto& u = lists[tile];
+      for (int k = 0; k < m.ustride; ++k)
+        m.tmem[(size_t)tile * m.ustride + k] = u.empty() ? 0 : u[std::min<size_t>(k, u.size() - 1)];
+    }
+  }
+
   // ---- reverse stencil lists for the adjoint gather ----
   const int R4 = d.rows4 * 4;
   m.rev_ptr.assign(nc + 1, 0);

@@ -69,7 +69,9 @@ struct teno_solver {
   Dims d;
   teno_params prm{};
   int n_cell = 0, n_pad = 0, n_tiles = 0;
-  int4* idx = nullptr;
+  int4* slot = nullptr;     // member slots of each tile's stencil rows (uint16)
+  int* tmem = nullptr;      // distinct stencil members of each tile
+  int ustride = 0;
   double2* M = nullptr;
   int4* nbinfo = nullptr;
   double* geo = nullptr;
@@ -167,7 +169,10 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
                        hipStream_t st, double* fp = nullptr) {
   ReconArgs a;
   a.U = U;
-  a.idx = s->idx;
+  a.slot = s->slot;
+  a.tmem = s->tmem;
+  a.ustride = s->ustride;
+  a.lds_stride = stage_int4(s->d.rows4, s->ustride);
   a.M = s->M;
   a.fp = fp ? fp : s->fp;
   a.flags = flags;
@@ -187,16 +192,17 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   a.cw_dK = 1.0 - 1.0 / s->prm.dk_prime;
   a.cw_ds = (1.0 - a.cw_dK) / 3.0;
   const int blocks = (s->n_tiles + 3) / 4;
+  const size_t lds = (size_t)4 * a.lds_stride * sizeof(int4);
   const bool cw = s->prm.variant == 2;
   int rc = TENO_OK;
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 0, st, [&]() {
       if (cw)
         hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value, true>),
-                           dim3(blocks), dim3(256), 0, st, a);
+                           dim3(blocks), dim3(256), lds, st, a);
       else
         hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value, false>),
-                           dim3(blocks), dim3(256), 0, st, a);
+                           dim3(blocks), dim3(256), lds, st, a);
     });
   });
   return rc;
@@ -446,7 +452,9 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
   auto A = [&](auto& p, size_t n) {
     if (rc == TENO_OK) rc = s->alloc(p, n);
   };
-  A(s->idx, m.idx.size() / 4);
+  s->ustride = m.ustride;
+  A(s->slot, m.slot.size() / 8);
+  A(s->tmem, m.tmem.size());
   A(s->M, m.M.size() / 2);
   A(s->nbinfo, np);
   s->n_face = m.nf;
@@ -478,7 +486,8 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
     void* dst;
     const void* src;
     size_t n;
-  } ups[] = {{s->idx, m.idx.data(), m.idx.size() * sizeof(int32_t)},
+  } ups[] = {{s->slot, m.slot.data(), m.slot.size() * sizeof(uint16_t)},
+             {s->tmem, m.tmem.data(), m.tmem.size() * sizeof(int32_t)},
              {s->M, m.M.data(), m.M.size() * sizeof(double)},
              {s->nbinfo, m.nbinfo.data(), m.nbinfo.size() * sizeof(int32_t)},
              {s->fcell, m.face_cells.data(), m.face_cells.size() * sizeof(int32_t)},
@@ -729,6 +738,7 @@ struct teno_batch {
   // launch plan: per reconstruction launch (pq, item offset, wave offset, waves)
   struct RLaunch {
     int pq, item0, wave0, n_waves;
+    int lds_stride;  // LDS per wavefront in int4, the largest of the launch's meshes
   };
   std::vector<RLaunch> rplan;
   int n_waves_f = 0, n_waves_c = 0, n_items_dt = 0;
@@ -825,10 +835,12 @@ int batch_plan(teno_batch* b) {
   for (int pq : pqs) {
     std::vector<double> cost;
     const int item0 = (int)items.size();
+    int lds_stride = 0;
     for (int m : morder) {
       const teno_solver* s = b->sv[m];
       const int mpq = s->d.order * 10 + s->d.nq;
       if (pq != 0 && mpq != pq) continue;
+      lds_stride = std::max(lds_stride, stage_int4(s->d.rows4, s->ustride));
       for (int t = 0; t < s->n_tiles; ++t) {
         items.push_back(make_int2(m, t));
         cost.push_back((double)s->d.Jp + 4.0 * s->d.rows4 * 4);
@@ -837,7 +849,7 @@ int batch_plan(teno_batch* b) {
     std::vector<int> st;
     const int nw = balanced_starts(cost, waves, st);
     for (int& x : st) x += item0;
-    b->rplan.push_back({pq, item0, (int)starts_all.size(), nw});
+    b->rplan.push_back({pq, item0, (int)starts_all.size(), nw, lds_stride});
     starts_all.insert(starts_all.end(), st.begin(), st.end());
   }
   // face items (64-face chunks), cell items (64-cell chunks) and dt items
@@ -911,7 +923,10 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
     for (int k = 0; k < 3; ++k) {
       ReconArgs& a = d.r[k];
       a.U = in[k];
-      a.idx = s->idx;
+      a.slot = s->slot;
+      a.tmem = s->tmem;
+      a.ustride = s->ustride;
+      a.lds_stride = stage_int4(s->d.rows4, s->ustride);
       a.M = s->M;
       a.fp = s->fp;
       a.flags = nullptr;
@@ -967,11 +982,12 @@ void batch_launch_recon(teno_batch* b, int k, hipStream_t st) {
   for (const auto& L : b->rplan) {
     const int blocks = (L.n_waves + 3) / 4;
     const int* ws = b->start_r + L.wave0;
+    const size_t lds = (size_t)4 * L.lds_stride * sizeof(int4);
     switch (L.pq) {
 #define TENO_BATCH_CASE(PQ)                                                                  \
   case PQ:                                                                                   \
-    hipLaunchKernelGGL((k_batch_reconstruct<PQ>), dim3(blocks), dim3(256), 0, st, b->meshes, \
-                       b->items_r, ws, L.n_waves, k);                                        \
+    hipLaunchKernelGGL((k_batch_reconstruct<PQ>), dim3(blocks), dim3(256), lds, st,          \
+                       b->meshes, b->items_r, ws, L.n_waves, k, L.lds_stride);               \
     break;
       TENO_BATCH_CASE(0)
       TENO_BATCH_CASE(32)
