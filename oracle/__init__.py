@@ -20,7 +20,8 @@ class Params(C.Structure):
     _fields_ = [("order", C.c_int32), ("nq", C.c_int32), ("variant", C.c_int32),
                 ("power", C.c_int32), ("ct", C.c_double), ("eps", C.c_double),
                 ("gamma", C.c_double), ("tie_rel", C.c_double),
-                ("fallback", C.c_int32), ("pad_", C.c_int32), ("dk_prime", C.c_double)]
+                ("fallback", C.c_int32), ("characteristic", C.c_int32),
+                ("dk_prime", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -67,6 +68,7 @@ def lib():
         L.oracle_basis.argtypes = [C.c_int, ip, ip, dp]
         L.oracle_select.argtypes = [C.POINTER(Params), dp, dp, ip]
         L.oracle_hll.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, dp]
+        L.oracle_char_basis.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.oracle_cweno_weights.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.oracle_reconstruct_cells.argtypes = [vp, dp, C.c_int, ip, dp, up, dp, C.POINTER(Diag)]
         L.oracle_residual.argtypes = [vp, dp, dp, up, C.c_int, dp, C.POINTER(Diag)]
@@ -107,10 +109,11 @@ def _check(rc):
 
 
 def params(order=5, ct=1e-6, eps=None, power=None, gamma=1.4, nq=0, variant=0, tie_rel=1e-10,
-           fallback=0, dk_prime=1e4):
+           fallback=0, dk_prime=1e4, characteristic=0):
     """Scheme parameters.  eps and power default to the paper's values of
     the variant: 1e-12 and 6 for TENO (Sec. 3.2), 1e-14 and 4 for CWENO
-    (variant 2, Sec. 2.4)."""
+    (variant 2, Sec. 2.4).  characteristic=1 selects in characteristic
+    variables, face by face (Sec. 2.3)."""
     if eps is None:
         eps = 1e-14 if variant == 2 else 1e-12
     if power is None:
@@ -120,6 +123,7 @@ def params(order=5, ct=1e-6, eps=None, power=None, gamma=1.4, nq=0, variant=0, t
         order, ct, eps, power, gamma, nq, variant, tie_rel
     p.fallback = fallback
     p.dk_prime = dk_prime
+    p.characteristic = characteristic
     return p
 
 
@@ -202,24 +206,34 @@ class OracleMesh:
         return m, rc.value
 
     # evaluation -------------------------------------------------------------
+    @property
+    def characteristic(self) -> bool:
+        return bool(self.prm is not None and self.prm.characteristic)
+
     def reconstruct_cells(self, U, cells):
+        """(fp [n][3][nq][4], flags, beta, diag).  flags: [n], or [n][3]
+        (one per local edge) in characteristic variables, where beta is
+        None."""
         U = _f64(U)
         c = np.ascontiguousarray(cells, dtype=np.int32)
         fp = np.empty((c.size, 3, self.nq, 4))
-        fl = np.empty(c.size, dtype=np.uint16)
+        fl = np.empty((c.size, 3) if self.characteristic else c.size, dtype=np.uint16)
         beta = np.empty((c.size, 4, 4))
         dg = Diag(0, -1, 0, 0, 0)
         _check(lib().oracle_reconstruct_cells(self.h, _d(U), c.size, _i(c), _d(fp), _u(fl),
                                               _d(beta), C.byref(dg)))
-        return fp, fl, beta, dg.as_dict()
+        return fp, fl, (None if self.characteristic else beta), dg.as_dict()
 
     def residual(self, U, frozen_flags=None, want_fp=False):
+        """flags: [n_cell], or [3][n_cell] (per local edge) in
+        characteristic variables."""
         U = _f64(U)
         R = np.empty_like(U)
         if frozen_flags is not None:
             fl = np.ascontiguousarray(frozen_flags, dtype=np.uint16).copy()
         else:
-            fl = np.empty(self.n_cell, dtype=np.uint16)
+            fl = np.empty((3, self.n_cell) if self.characteristic else self.n_cell,
+                          dtype=np.uint16)
         fp = np.empty((self.n_cell, 3, self.nq, 4)) if want_fp else None
         dg = Diag(0, -1, 0, 0, 0)
         _check(lib().oracle_residual(self.h, _d(U), _d(R), _u(fl),
@@ -234,7 +248,7 @@ class OracleMesh:
         U = _f64(U)
         c = np.ascontiguousarray(cells, dtype=np.int32)
         R = np.empty((c.size, 4))
-        fl = np.empty(c.size, dtype=np.uint16)
+        fl = np.empty((c.size, 3) if self.characteristic else c.size, dtype=np.uint16)
         _check(lib().oracle_residual_cells(self.h, _d(U), c.size, _i(c), _d(R), _u(fl)))
         return R, fl
 
@@ -247,7 +261,8 @@ class OracleMesh:
         if frozen_flags3 is not None:
             fl = np.ascontiguousarray(frozen_flags3, dtype=np.uint16).copy()
         else:
-            fl = np.empty((3, self.n_cell), dtype=np.uint16)
+            fl = np.empty((3, 3, self.n_cell) if self.characteristic else (3, self.n_cell),
+                          dtype=np.uint16)
         st = np.empty((3,) + U.shape) if want_stages else None
         dg = Diag(0, -1, 0, 0, 0)
         _check(lib().oracle_rk_step(self.h, _d(U), _d(out), float(dt), _u(fl),
@@ -325,6 +340,14 @@ def cweno_weights(beta, prm: Params):
     d = np.empty(4)
     lib().oracle_cweno_weights(C.byref(prm), _d(b), _d(w), _d(d))
     return w, d
+
+
+def char_basis(u, n, gamma=1.4):
+    """(R, L): right eigenvectors (columns) of the Euler flux Jacobian in
+    direction n at state u, and L = R^-1; identity for a non-physical u."""
+    R, L = np.empty((4, 4)), np.empty((4, 4))
+    lib().oracle_char_basis(_d(_f64(u)), float(n[0]), float(n[1]), float(gamma), _d(R), _d(L))
+    return R, L
 
 
 def hll(uL, uR, n, gamma=1.4):

@@ -41,6 +41,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -60,7 +61,7 @@ typedef struct oracle_params {
   double tie_rel;   // near-tie band |chi/C_T - 1| <= tie_rel
   int32_t fallback; // 1: a cell with a non-physical face point uses its cell
                     // average on every face (flags 0); 0: paper as stated
-  int32_t pad_;
+  int32_t characteristic;  // 1: select in characteristic variables, per face
   double dk_prime;  // CWENO: d_K = 1 - 1/dk_prime (paper: 1e4)
 } oracle_params;
 
@@ -623,6 +624,57 @@ void note_bad(oracle_diag* dg, int cell) {
 }
 
 // ---------------------------------------------------------------------------
+// Least-squares coefficients of variable v of cell i on its four stencils
+// (Sec. 2.2 eqs. 08-10): right-hand side |V'_s| (U_s - U_0), QR solve.
+// ---------------------------------------------------------------------------
+template <class T>
+void lsq_coefficients(const CellData& cd, const T* U, int i, int v, std::vector<T> coef[4]) {
+  const T u0 = U[4 * i + v];
+  for (int k = 0; k < 4; ++k) {
+    const Stencil& S = cd.st[k];
+    std::vector<T> b(S.qr.m);
+    for (int s = 0; s < S.qr.m; ++s) b[s] = S.vol[s] * (U[4 * S.cells[s] + v] - u0);
+    coef[k].assign(S.qr.n, T(0.0));
+    qr_solve(S.qr, b.data(), coef[k].data());
+  }
+}
+
+// Combined coefficients of the TENO selection with flags f4 (Sec. 3.3): the
+// large stencil's, else the mean of the kept small stencils' (zero when none
+// is kept, which only the first-order fallback produces).
+template <class T>
+void teno_combine(unsigned f4, const std::vector<T> coef[4], int nb, int ns, std::vector<T>& abar) {
+  abar.assign(nb, T(0.0));
+  if (f4 & 8u) {
+    for (int l = 0; l < nb; ++l) abar[l] = coef[3][l];
+    return;
+  }
+  int cnt = (int)((f4 & 1u) + ((f4 >> 1) & 1u) + ((f4 >> 2) & 1u));
+  for (int l = 0; l < ns && cnt > 0; ++l) {
+    T acc = T(0.0);
+    for (int k = 0; k < 3; ++k)
+      if (f4 & (1u << k)) acc += coef[k][l];
+    abar[l] = acc / (double)cnt;
+  }
+}
+
+// Combined coefficients of CWENO (Sec. 2.4):
+// P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k.
+template <class T>
+void cweno_combine(const double w[4], const double d[4], const std::vector<T> coef[4], int nb, int ns,
+                   std::vector<T>& abar) {
+  abar.assign(nb, T(0.0));
+  for (int l = 0; l < nb; ++l) {
+    T opt = coef[3][l];
+    if (l < ns)
+      for (int k = 0; k < 3; ++k) opt -= d[k] * coef[k][l];
+    abar[l] = (w[3] / d[3]) * opt;
+    if (l < ns)
+      for (int k = 0; k < 3; ++k) abar[l] += w[k] * coef[k][l];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Reconstruction of one cell (all four variables); templated for complex step.
 // fp gets [3][nq][4]; flags in/out (frozen when `frozen` is true).
 // ---------------------------------------------------------------------------
@@ -635,13 +687,7 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
   for (int v = 0; v < 4; ++v) {
     T u0 = U[4 * i + v];
     std::vector<T> coef[4];
-    for (int k = 0; k < 4; ++k) {
-      const Stencil& S = cd.st[k];
-      std::vector<T> b(S.qr.m);
-      for (int s = 0; s < S.qr.m; ++s) b[s] = S.vol[s] * (U[4 * S.cells[s] + v] - u0);
-      coef[k].assign(S.qr.n, T(0.0));
-      qr_solve(S.qr, b.data(), coef[k].data());
-    }
+    lsq_coefficients(cd, U, i, v, coef);
     if (m.prm.variant == 2) {
       // CWENO (Sec. 2.4): P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k
       double beta[4], w[4], d[4];
@@ -652,15 +698,8 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
       }
       if (beta_out) for (int k = 0; k < 4; ++k) beta_out[4 * v + k] = beta[k];
       cweno_weights(beta, m.prm, w, d);
-      std::vector<T> abar(nb, T(0.0));
-      for (int l = 0; l < nb; ++l) {
-        T opt = coef[3][l];
-        if (l < ns)
-          for (int k = 0; k < 3; ++k) opt -= d[k] * coef[k][l];
-        abar[l] = (w[3] / d[3]) * opt;
-        if (l < ns)
-          for (int k = 0; k < 3; ++k) abar[l] += w[k] * coef[k][l];
-      }
+      std::vector<T> abar;
+      cweno_combine(w, d, coef, nb, ns, abar);
       for (int e = 0; e < 3; ++e)
         for (int kq = 0; kq < m.nq; ++kq) {
           double xi, eta;
@@ -690,19 +729,8 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
       }
     }
     out_flags |= (uint16_t)(f4 << (4 * v));
-    std::vector<T> abar(nb, T(0.0));
-    if (f4 & 8u) {
-      for (int l = 0; l < nb; ++l) abar[l] = coef[3][l];
-    } else {
-      // no stencil kept (only after the first-order fallback): abar = 0
-      int cnt = (int)((f4 & 1u) + ((f4 >> 1) & 1u) + ((f4 >> 2) & 1u));
-      for (int l = 0; l < ns && cnt > 0; ++l) {
-        T acc = T(0.0);
-        for (int k = 0; k < 3; ++k)
-          if (f4 & (1u << k)) acc += coef[k][l];
-        abar[l] = acc / (double)cnt;
-      }
-    }
+    std::vector<T> abar;
+    teno_combine(f4, coef, nb, ns, abar);
     for (int e = 0; e < 3; ++e)
       for (int kq = 0; kq < m.nq; ++kq) {
         double xi, eta;
@@ -732,6 +760,160 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
     }
   }
   flags = out_flags;
+}
+
+// +1 when cell i is the L side of the face on its local edge e (the face
+// normal points out of i), else -1.
+double side_sign(const Mesh& m, int i, int e) {
+  const int f = m.cf[3 * i + e];
+  double s = (m.fL[f] == i && m.fLe[f] == e) ? 1.0 : -1.0;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic variables (Sec. 2.3, remark on which variables the
+// nonlinear reconstruction acts on).  Reading: on local edge e of cell i the
+// variables are w = L U with R = L^-1 the right eigenvectors of the Euler
+// flux Jacobian in the direction of the edge's outward unit normal n,
+// evaluated at the cell's mean state; a non-physical mean (no real sound
+// speed) keeps the conservative variables (L = R = I).  Every face of the
+// cell has its own projection, selection and flags.
+// ---------------------------------------------------------------------------
+
+// R (row-major, R[4*row + col]); column k is the right eigenvector of speed
+// u.n - c, u.n (entropy), u.n (shear), u.n + c.
+void char_right(const double* u, double nx, double ny, double g, double* R) {
+  const double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+  const double q2 = vx * vx + vy * vy;
+  const double p = (g - 1.0) * (u[3] - 0.5 * rho * q2);
+  const double c = std::sqrt(g * p / rho);
+  const double H = (u[3] + p) / rho;
+  const double un = vx * nx + vy * ny, ut = -vx * ny + vy * nx;
+  const double cols[4][4] = {{1.0, vx - c * nx, vy - c * ny, H - c * un},
+                             {1.0, vx, vy, 0.5 * q2},
+                             {0.0, -ny, nx, ut},
+                             {1.0, vx + c * nx, vy + c * ny, H + c * un}};
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 4; ++k) R[4 * r + k] = cols[k][r];
+}
+
+// Inverse of a 4x4 matrix by Gauss-Jordan elimination with partial pivoting.
+bool invert4(const double* A, double* Ainv) {
+  double a[4][8];
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 8; ++k) a[r][k] = k < 4 ? A[4 * r + k] : (k - 4 == r ? 1.0 : 0.0);
+  for (int col = 0; col < 4; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 4; ++r)
+      if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+    if (!(std::fabs(a[piv][col]) > 0.0)) return false;
+    if (piv != col)
+      for (int k = 0; k < 8; ++k) std::swap(a[piv][k], a[col][k]);
+    const double d = a[col][col];
+    for (int k = 0; k < 8; ++k) a[col][k] /= d;
+    for (int r = 0; r < 4; ++r) {
+      if (r == col) continue;
+      const double f = a[r][col];
+      for (int k = 0; k < 8; ++k) a[r][k] -= f * a[col][k];
+    }
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 4; ++k) Ainv[4 * r + k] = a[r][k + 4];
+  return true;
+}
+
+// L and R of cell state u for direction n; identity when u is not physical.
+void char_basis(const double* u, double nx, double ny, double g, double* R, double* L) {
+  bool ok = physical(u, g);
+  if (ok) {
+    char_right(u, nx, ny, g, R);
+    ok = invert4(R, L);
+  }
+  if (!ok)
+    for (int t = 0; t < 16; ++t) R[t] = L[t] = (t % 5 == 0) ? 1.0 : 0.0;
+}
+
+// Outward unit normal of local edge e of cell i.
+void edge_normal(const Mesh& m, int i, int e, double& nx, double& ny) {
+  const int f = m.cf[3 * i + e];
+  const double s = side_sign(m, i, e);
+  nx = s * m.fn[2 * f];
+  ny = s * m.fn[2 * f + 1];
+}
+
+// Characteristic reconstruction of one cell: fp [3][nq][4], flags3[e] = the
+// flags of local edge e (bit 4v+3: large stencil kept for characteristic
+// variable v, bits 4v..4v+2: small stencils kept).
+void reconstruct_cell_char(const Mesh& m, int i, const double* U, uint16_t* flags3, double* fp,
+                           oracle_diag* dg) {
+  const CellData& cd = m.cd[i];
+  const int nb = m.big.n(), ns = m.small.n();
+  // least-squares coefficients of the conservative variables (linear in
+  // the data, so those of w = L U are L times these)
+  std::vector<double> coef[4][4];  // [variable][stencil]
+  for (int v = 0; v < 4; ++v) lsq_coefficients(cd, U, i, v, coef[v]);
+  const double* u0 = &U[4 * i];
+  for (int e = 0; e < 3; ++e) {
+    double nx, ny, R[16], L[16];
+    edge_normal(m, i, e, nx, ny);
+    char_basis(u0, nx, ny, m.prm.gamma, R, L);
+    uint16_t fe = 0;
+    std::vector<double> dw[4];  // per characteristic variable: value minus mean at the points
+    for (int v = 0; v < 4; ++v) {
+      std::vector<double> wc[4];
+      double beta[4];
+      for (int k = 0; k < 4; ++k) {
+        wc[k].assign(coef[0][k].size(), 0.0);
+        for (size_t l = 0; l < wc[k].size(); ++l)
+          for (int j = 0; j < 4; ++j) wc[k][l] += L[4 * v + j] * coef[j][k][l];
+        beta[k] = smoothness(k == 3 ? m.big : m.small, wc[k].data());
+      }
+      std::vector<double> abar;
+      if (m.prm.variant == 2) {
+        double w[4], d[4];
+        cweno_weights(beta, m.prm, w, d);
+        cweno_combine(w, d, wc, nb, ns, abar);
+      } else {
+        Sel s = select(beta, m.prm);
+        if (dg) {
+          dg->near_ties += s.ties;
+          if (s.flags & 8u) dg->large_kept++;
+        }
+        fe |= (uint16_t)(s.flags << (4 * v));
+        teno_combine(s.flags, wc, nb, ns, abar);
+      }
+      dw[v].assign(m.nq, 0.0);
+      for (int kq = 0; kq < m.nq; ++kq) {
+        double xi, eta;
+        face_point(e, m.gq_t[kq], xi, eta);
+        for (int l = 0; l < nb; ++l) dw[v][kq] += abar[l] * psi(m.big, l, xi, eta);
+      }
+    }
+    flags3[e] = fe;
+    // back to conservative variables: U = U_0 + R dw
+    for (int kq = 0; kq < m.nq; ++kq)
+      for (int c = 0; c < 4; ++c) {
+        double val = u0[c];
+        for (int v = 0; v < 4; ++v) val += R[4 * c + v] * dw[v][kq];
+        fp[(e * m.nq + kq) * 4 + c] = val;
+      }
+  }
+  // non-physical states, as in the conservative reconstruction
+  double u[4];
+  for (int c = 0; c < 4; ++c) u[c] = u0[c];
+  bool avg_ok = physical(u, m.prm.gamma);
+  bool fp_ok = true;
+  for (int q = 0; q < 3 * m.nq && fp_ok; ++q) {
+    for (int c = 0; c < 4; ++c) u[c] = fp[q * 4 + c];
+    fp_ok = physical(u, m.prm.gamma);
+  }
+  if (!(avg_ok && fp_ok)) note_bad(dg, i);
+  if (!fp_ok && avg_ok && m.prm.fallback) {
+    for (int q = 0; q < 3 * m.nq; ++q)
+      for (int c = 0; c < 4; ++c) fp[q * 4 + c] = u0[c];
+    flags3[0] = flags3[1] = flags3[2] = 0;
+    if (dg) dg->fallbacks++;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -805,7 +987,7 @@ void assemble(const Mesh& m, const std::vector<T>& phi, int i, T* Ri) {
   T acc[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
   for (int e = 0; e < 3; ++e) {
     int f = m.cf[3 * i + e];
-    double s = (m.fL[f] == i && m.fLe[f] == e) ? 1.0 : -1.0;
+    double s = side_sign(m, i, e);
     for (int c = 0; c < 4; ++c) acc[c] += s * phi[4 * (size_t)f + c];
   }
   for (int c = 0; c < 4; ++c) Ri[c] = -acc[c] / m.area[i];
@@ -815,14 +997,22 @@ template <class T>
 void residual_full(const Mesh& m, const T* U, T* R, uint16_t* flags, bool frozen,
                    double* fp_out, oracle_diag* dg) {
   const int nq = m.nq;
+  const bool chr = m.prm.characteristic != 0;  // flags per local edge, never frozen
   std::vector<T> fp((size_t)m.nc * 3 * nq * 4);
-  std::vector<uint16_t> fl(m.nc, 0);
+  std::vector<uint16_t> fl((size_t)m.nc * (chr ? 3 : 1), 0);
   if (frozen) for (int i = 0; i < m.nc; ++i) fl[i] = flags[i];
   int64_t nt = 0, lk = 0, fb = 0, nbad = 0, first = m.nc;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : nt, lk, fb, nbad) reduction(min : first)
   for (int i = 0; i < m.nc; ++i) {
     oracle_diag local{0, -1, 0, 0, 0};
-    reconstruct_cell(m, i, U, frozen, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, &local);
+    if constexpr (std::is_same<T, double>::value) {
+      if (chr)
+        reconstruct_cell_char(m, i, U, &fl[3 * (size_t)i], &fp[(size_t)i * 3 * nq * 4], &local);
+      else
+        reconstruct_cell(m, i, U, frozen, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, &local);
+    } else {
+      reconstruct_cell(m, i, U, frozen, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, &local);
+    }
     nt += local.near_ties;
     lk += local.large_kept;
     fb += local.fallbacks;
@@ -843,8 +1033,14 @@ void residual_full(const Mesh& m, const T* U, T* R, uint16_t* flags, bool frozen
   for (int f = 0; f < m.nf; ++f) face_flux(m, f, fp.data(), &phi[4 * (size_t)f]);
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < m.nc; ++i) assemble(m, phi, i, &R[4 * (size_t)i]);
-  if (flags && !frozen)
-    for (int i = 0; i < m.nc; ++i) flags[i] = fl[i];
+  if (flags && !frozen) {
+    if (chr) {
+      for (int e = 0; e < 3; ++e)
+        for (int i = 0; i < m.nc; ++i) flags[(size_t)e * m.nc + i] = fl[3 * (size_t)i + e];
+    } else {
+      for (int i = 0; i < m.nc; ++i) flags[i] = fl[i];
+    }
+  }
 }
 
 bool ready(const Mesh& m) {
@@ -887,7 +1083,7 @@ void oracle_default_params(oracle_params* p) {
   p->gamma = 1.4;
   p->tie_rel = 1e-10;
   p->fallback = 0;
-  p->pad_ = 0;
+  p->characteristic = 0;
   p->dk_prime = 1e4;
 }
 
@@ -1018,6 +1214,7 @@ int oracle_setup(void* h, const oracle_params* p, int all) {
   if (p->order < 3 || p->order > 6) return fail("order must be 3..6");
   if (p->variant < 0 || p->variant > 2) return fail("variant must be 0, 1 or 2");
   if (p->variant == 2 && !(p->dk_prime > 1.0)) return fail("CWENO needs dk_prime > 1");
+  if (p->characteristic != 0 && p->characteristic != 1) return fail("characteristic must be 0 or 1");
   if (p->ct < 0.0 || p->ct > 1.0 / 3.0) return fail("C_T must lie in [0, 1/K]");
   m->prm = *p;
   m->nq = p->nq > 0 ? p->nq : (p->order + 1) / 2;
@@ -1185,12 +1382,19 @@ void oracle_cweno_weights(const oracle_params* p, const double* beta, double* om
 }
 
 // HLL flux through unit normal n (Sec. 4).
+// Right and left eigenvectors (row-major 4x4) of the flux Jacobian in the
+// direction (nx, ny) at state u; identity for a non-physical state.
+void oracle_char_basis(const double* u, double nx, double ny, double g, double* R, double* L) {
+  char_basis(u, nx, ny, g, R, L);
+}
+
 void oracle_hll(const double* uL, const double* uR, double nx, double ny, double g, double* out) {
   hll_flux(uL, uR, nx, ny, g, out);
 }
 
 // Reconstructed face-point states of listed cells: fp [n][3][nq][4],
-// flags [n], beta [n][4 vars][4 stencils] (nullable).
+// flags [n] ([n][3], one per local edge, in characteristic variables), beta
+// [n][4 vars][4 stencils] (nullable; conservative variables only).
 int oracle_reconstruct_cells(void* h, const double* U, int n, const int* cells, double* fp,
                              uint16_t* flags, double* beta, oracle_diag* dg) {
   Mesh* m = (Mesh*)h;
@@ -1201,10 +1405,17 @@ int oracle_reconstruct_cells(void* h, const double* U, int n, const int* cells, 
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : nt, lk, fb, nbad)
   for (int t = 0; t < n; ++t) {
     oracle_diag local{0, -1, 0, 0, 0};
-    uint16_t fl = 0;
-    reconstruct_cell(*m, cells[t], U, false, fl, &fp[(size_t)t * 3 * nq * 4],
-                     beta ? &beta[(size_t)t * 16] : nullptr, &local);
-    if (flags) flags[t] = fl;
+    if (m->prm.characteristic) {
+      uint16_t fl3[3] = {0, 0, 0};
+      reconstruct_cell_char(*m, cells[t], U, fl3, &fp[(size_t)t * 3 * nq * 4], &local);
+      if (flags)
+        for (int e = 0; e < 3; ++e) flags[3 * (size_t)t + e] = fl3[e];
+    } else {
+      uint16_t fl = 0;
+      reconstruct_cell(*m, cells[t], U, false, fl, &fp[(size_t)t * 3 * nq * 4],
+                       beta ? &beta[(size_t)t * 16] : nullptr, &local);
+      if (flags) flags[t] = fl;
+    }
     nt += local.near_ties;
     lk += local.large_kept;
     fb += local.fallbacks;
@@ -1219,13 +1430,15 @@ int oracle_reconstruct_cells(void* h, const double* U, int n, const int* cells, 
   return 0;
 }
 
-// Full residual R[nc][4]; flags[nc] out (or in when frozen=1); fp_out
+// Full residual R[nc][4]; flags[nc] out (or in when frozen=1; in
+// characteristic variables [3][nc], one per local edge, out only); fp_out
 // [nc][3][nq][4] nullable; diag nullable.
 int oracle_residual(void* h, const double* U, double* R, uint16_t* flags, int frozen,
                     double* fp_out, oracle_diag* dg) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   if (frozen && !flags) return fail("frozen selection needs flags");
+  if (frozen && m->prm.characteristic) return fail("no frozen selection in characteristic variables");
   for (int i = 0; i < m->nc; ++i)
     if (!m->cd[i].built) return fail("oracle_setup(all=1) required for the full residual");
   residual_full(*m, U, R, flags, frozen != 0, fp_out, dg);
@@ -1251,11 +1464,16 @@ int oracle_residual_cells(void* h, const double* U, int n, const int* cells, dou
   std::sort(need.begin(), need.end());
   need.erase(std::unique(need.begin(), need.end()), need.end());
   if (oracle_prepare_cells(h, (int)need.size(), need.data()) != 0) return -1;
+  const int fw = m->prm.characteristic ? 3 : 1;
   std::vector<double> fpn(need.size() * 3 * nq * 4);
-  std::vector<uint16_t> fln(need.size(), 0);
+  std::vector<uint16_t> fln(need.size() * fw, 0);
 #pragma omp parallel for schedule(dynamic, 16)
-  for (size_t t = 0; t < need.size(); ++t)
-    reconstruct_cell(*m, need[t], U, false, fln[t], &fpn[t * 3 * nq * 4], nullptr, nullptr);
+  for (size_t t = 0; t < need.size(); ++t) {
+    if (fw == 3)
+      reconstruct_cell_char(*m, need[t], U, &fln[3 * t], &fpn[t * 3 * nq * 4], nullptr);
+    else
+      reconstruct_cell(*m, need[t], U, false, fln[t], &fpn[t * 3 * nq * 4], nullptr, nullptr);
+  }
   auto slot = [&](int c) {
     return (size_t)(std::lower_bound(need.begin(), need.end(), c) - need.begin());
   };
@@ -1278,7 +1496,8 @@ int oracle_residual_cells(void* h, const double* U, int n, const int* cells, dou
       for (int c = 0; c < 4; ++c) acc[c] += s * (phi[c] * m->flen[f]);
     }
     for (int c = 0; c < 4; ++c) R_out[4 * (size_t)t + c] = -acc[c] / m->area[i];
-    if (flags_out) flags_out[t] = fln[slot(i)];
+    if (flags_out)
+      for (int w = 0; w < fw; ++w) flags_out[(size_t)t * fw + w] = fln[slot(i) * fw + w];
   }
   return 0;
 }
@@ -1306,22 +1525,24 @@ double oracle_dt(void* h, const double* U, double cfl) {
 }
 
 // One SSP-RK3 step (Sec. 2.1, time discretisation); flags3 [3][nc] nullable
-// (out, or in when frozen=1); stages [3][nc][4] nullable (stage inputs).
+// (out, or in when frozen=1; [3][3][nc] out in characteristic variables);
+// stages [3][nc][4] nullable (stage inputs).
 int oracle_rk_step(void* h, const double* U, double* Uout, double dt, uint16_t* flags3,
                    int frozen, double* stages, oracle_diag* dg) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   const size_t n4 = 4 * (size_t)m->nc;
   std::vector<double> R(n4), U1(n4), U2(n4);
-  std::vector<uint16_t> fl(m->nc);
+  const size_t nfl = (size_t)m->nc * (m->prm.characteristic ? 3 : 1);
+  std::vector<uint16_t> fl(nfl);
   auto stage_flags = [&](int s) -> uint16_t* {
     if (frozen) {
-      std::copy(flags3 + (size_t)s * m->nc, flags3 + (size_t)(s + 1) * m->nc, fl.begin());
+      std::copy(flags3 + (size_t)s * nfl, flags3 + (size_t)(s + 1) * nfl, fl.begin());
     }
     return fl.data();
   };
   auto keep = [&](int s) {
-    if (flags3 && !frozen) std::copy(fl.begin(), fl.end(), flags3 + (size_t)s * m->nc);
+    if (flags3 && !frozen) std::copy(fl.begin(), fl.end(), flags3 + (size_t)s * nfl);
   };
   if (stages) std::copy(U, U + n4, stages);
   if (oracle_residual(h, U, R.data(), stage_flags(0), frozen, nullptr, dg)) return -1;
@@ -1345,6 +1566,7 @@ int oracle_jvp(void* h, const double* U, const uint16_t* flags, const double* v,
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
+  if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
   const size_t n4 = 4 * (size_t)m->nc;
   const double hh = 1e-30;
   std::vector<cplx> Uc(n4), Rc(n4);
@@ -1360,6 +1582,7 @@ int oracle_vjp(void* h, const double* U, const uint16_t* flags, const double* la
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
+  if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
   const int nq = m->nq, nc = m->nc;
   const size_t n4 = 4 * (size_t)nc;
   // forward face points with the frozen selection

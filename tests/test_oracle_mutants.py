@@ -68,6 +68,19 @@ MUTANTS = [
     ("cweno_optimal_subtraction", "for (int k = 0; k < 3; ++k) opt -= d[k] * coef[k][l];",
      "for (int k = 0; k < 3; ++k) opt += d[k] * coef[k][l];"),
     ("cweno_large_scaling", "abar[l] = (w[3] / d[3]) * opt;", "abar[l] = w[3] * opt;"),
+    ("char_acoustic_energy", "{1.0, vx - c * nx, vy - c * ny, H - c * un},",
+     "{1.0, vx - c * nx, vy - c * ny, H + c * un},"),
+    ("char_shear_energy", "{0.0, -ny, nx, ut},", "{0.0, -ny, nx, un},"),
+    ("char_inverse_elimination", "for (int k = 0; k < 8; ++k) a[r][k] -= f * a[col][k];",
+     "for (int k = 0; k < 8; ++k) a[r][k] += f * a[col][k];"),
+    ("char_face_normal", "    edge_normal(m, i, e, nx, ny);\n",
+     "    edge_normal(m, i, (e + 1) % 3, nx, ny);\n"),
+    ("char_projection_state", "char_basis(u0, nx, ny, m.prm.gamma, R, L);",
+     "char_basis(&U[4 * (size_t)cd.st[3].cells[1]], nx, ny, m.prm.gamma, R, L);"),
+    ("char_projection_transposed", "wc[k][l] += L[4 * v + j] * coef[j][k][l];",
+     "wc[k][l] += L[4 * j + v] * coef[j][k][l];"),
+    ("char_back_transform", "val += R[4 * c + v] * dw[v][kq];", "val += L[4 * c + v] * dw[v][kq];"),
+    ("char_flags_edge", "    flags3[e] = fe;\n", "    flags3[(e + 1) % 3] = fe;\n"),
 ]
 
 

@@ -693,3 +693,169 @@ def test_nonphysical_detection_and_fallback(oracle_mod):
     np.testing.assert_array_equal(on["fp"][bad], np.broadcast_to(U[bad][:, None, None, :], on["fp"][bad].shape))
     np.testing.assert_array_equal(on["fp"][~bad], fp[~bad])
     assert np.isfinite(on["R"]).all()
+
+
+# --------------------------------------------------------------------------
+# characteristic variables (Sec. 2.3): per-face eigenvector projection
+# --------------------------------------------------------------------------
+def _flux_jacobian(u, n, g=1.4):
+    """Jacobian of the Euler flux in direction n, by complex step (exact to
+    rounding, independent of any eigenvector formula)."""
+    h = 1e-40
+    A = np.empty((4, 4))
+    for j in range(4):
+        uc = np.array(u, dtype=complex)
+        uc[j] += 1j * h
+        A[:, j] = _euler_normal_flux(uc, n, g).imag / h
+    return A
+
+
+def test_char_basis_diagonalises_the_flux_jacobian(oracle_mod):
+    rng = np.random.default_rng(31)
+    for _ in range(40):
+        g = rng.choice([1.4, 5.0 / 3.0])
+        rho, p = rng.uniform(0.1, 5.0), rng.uniform(0.1, 5.0)
+        vx, vy = rng.normal(size=2)
+        th = rng.uniform(0, 2 * np.pi)
+        n = np.array([np.cos(th), np.sin(th)])
+        u = _state(rho, vx, vy, p, g)
+        R, L = oracle_mod.char_basis(u, n, g)
+        A = _flux_jacobian(u, n, g)
+        c, un = np.sqrt(g * p / rho), vx * n[0] + vy * n[1]
+        lam = np.array([un - c, un, un, un + c])
+        scale = np.abs(A).max() * np.abs(R).max()
+        assert np.abs(A @ R - R * lam).max() <= 1e-13 * scale
+        assert np.abs(L @ R - np.eye(4)).max() <= 1e-13 * np.abs(L).max() * np.abs(R).max()
+        assert np.linalg.matrix_rank(R) == 4
+    # no real sound speed: the conservative variables are kept
+    R, L = oracle_mod.char_basis(np.array([1.0, 0.0, 0.0, -1.0]), (1.0, 0.0))
+    np.testing.assert_array_equal(R, np.eye(4))
+    np.testing.assert_array_equal(L, np.eye(4))
+
+
+def _unwrapped_ccw(m, tri, i):
+    v = m.xy[tri[i]]
+    return v[0] + (v - v[0]) - np.round(v - v[0])
+
+
+@pytest.mark.parametrize("order,variant", [(4, 0), (5, 0), (5, 2)])
+def test_char_reconstruction_is_componentwise_on_the_projected_field(oracle_mod, order, variant):
+    """On local edge e of cell i the characteristic reconstruction is the
+    conservative one applied to the field w = L U, mapped back as
+    U_0 + R (w - w_0), with L, R taken at U_i for the edge's outward normal
+    (computed here from the vertices)."""
+    m = inputs.jittered_periodic_mesh(10, 41)
+    U = inputs.random_lines(m)
+    oc = oracle_mod.OracleMesh(m.xy, m.tri).setup(
+        oracle_mod.params(order=order, variant=variant, characteristic=1), all_cells=False)
+    ov = oracle_mod.OracleMesh(m.xy, m.tri).setup(
+        oracle_mod.params(order=order, variant=variant), all_cells=False)
+    _, _, tri = ov.geometry()
+    cells = np.arange(3, ov.n_cell, 17)
+    fp, fl, beta, dg = oc.reconstruct_cells(U, cells)
+    assert beta is None and fl.shape == (cells.size, 3)
+    assert dg["near_ties"] == 0
+    dropped = 0
+    for t, i in enumerate(cells):
+        v = _unwrapped_ccw(m, tri, i)
+        for e in range(3):
+            d = v[(e + 1) % 3] - v[e]
+            n = np.array([d[1], -d[0]]) / np.hypot(*d)
+            R, L = oracle_mod.char_basis(U[i], n)
+            W = U @ L.T
+            fw, flw, _, dgw = ov.reconstruct_cells(W, [i])
+            assert dgw["near_ties"] == 0
+            expect = U[i] + (fw[0, e] - W[i]) @ R.T
+            scale = np.abs(U[i]).max()
+            assert np.abs(fp[t, e] - expect).max() <= 1e-12 * scale, (i, e)
+            assert fl[t, e] == flw[0], (i, e)
+            dropped += variant == 0 and flw[0] != 0x8888
+    assert variant != 0 or dropped > 0
+
+
+def test_char_contact_keeps_velocity_and_pressure(oracle_mod):
+    """A contact (density jumps, velocity and pressure uniform) lies in one
+    characteristic field only: the other three see constant data, so the
+    face states keep the uniform velocity and pressure whatever is selected."""
+    m = inputs.jittered_periodic_mesh(12, 43)
+    cen = m.xy[m.tri].mean(1)
+    rho = np.where(np.sin(2 * np.pi * (cen[:, 0] + 0.3 * cen[:, 1])) > 0, 3.0, 1.0)
+    rho = rho + 0.2 * np.cos(2 * np.pi * cen[:, 1])
+    vx, vy, p = 0.7, -0.3, 1.0
+    U = np.stack([rho, rho * vx, rho * vy, p / 0.4 + 0.5 * rho * (vx * vx + vy * vy)], 1)
+    oc = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=5, characteristic=1))
+    r = oc.residual(U, want_fp=True)
+    fp = r["fp"]
+    ux, uy = fp[..., 1] / fp[..., 0], fp[..., 2] / fp[..., 0]
+    pf = 0.4 * (fp[..., 3] - 0.5 * fp[..., 0] * (ux * ux + uy * uy))
+    assert np.abs(ux - vx).max() < 1e-12 and np.abs(uy - vy).max() < 1e-12
+    assert np.abs(pf - p).max() < 1e-12
+    fl = r["flags"]
+    assert fl.shape == (3, oc.n_cell)
+    # the entropy field (variable 1) drops the large stencil at the jumps,
+    # the acoustic and shear fields (0, 2, 3) keep it everywhere
+    assert ((fl >> 4) & 0xF != 8).any()
+    for v in (0, 2, 3):
+        assert ((fl >> (4 * v)) & 0xF == 8).all()
+
+
+def test_char_linear_variant_is_the_conservative_one(oracle_mod):
+    m = inputs.jittered_periodic_mesh(10, 45)
+    U = inputs.random_lines(m)
+    a = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=4, variant=1, characteristic=1))
+    b = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=4, variant=1))
+    ra, rb = a.residual(U, want_fp=True), b.residual(U, want_fp=True)
+    # (sharp data: some face states are not physical, so compare the states)
+    assert np.abs(ra["fp"] - rb["fp"]).max() <= 1e-12 * np.abs(rb["fp"]).max()
+    assert (ra["flags"] == 0x8888).all()
+
+
+def test_char_equals_conservative_where_every_field_is_smooth(oracle_mod):
+    w, m, U = inputs.make_workload(1)
+    a = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=3, characteristic=1))
+    b = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=3))
+    ra, rb = a.residual(U), b.residual(U)
+    assert (ra["flags"] == 0x8888).all() and (rb["flags"] == 0x8888).all()
+    assert np.abs(ra["R"] - rb["R"]).max() <= 1e-11 * np.abs(rb["R"]).max()
+
+
+def test_char_rotation_covariance(oracle_mod):
+    # the characteristic fields of a face do not change under a rotation of
+    # mesh and velocity, so neither do any of the selections
+    m = inputs.jittered_periodic_mesh(10, 47)
+    U = inputs.random_lines(m)
+    prm = dict(order=4, fallback=1, characteristic=1)
+    r0 = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(**prm)).residual(U)
+    xy = np.stack([-m.xy[:, 1], m.xy[:, 0]], 1)
+    Ur = U[:, [0, 2, 1, 3]] * [1, -1, 1, 1]
+    r1 = oracle_mod.OracleMesh(xy, m.tri).setup(oracle_mod.params(**prm)).residual(Ur)
+    Rr = r0["R"][:, [0, 2, 1, 3]] * [1, -1, 1, 1]
+    assert np.abs(r1["R"] - Rr).max() < 1e-11 * np.abs(r0["R"]).max()
+    np.testing.assert_array_equal(r1["flags"], r0["flags"])
+    assert (r0["flags"] != 0x8888).any()
+
+
+def test_char_nonphysical_mean_keeps_conservative_variables(oracle_mod):
+    m = inputs.jittered_periodic_mesh(10, 49)
+    U = inputs.random_lines(m)
+    i = 37
+    U[i, 3] = 0.5 * (U[i, 1] ** 2 + U[i, 2] ** 2) / U[i, 0] - 0.1   # p < 0
+    a = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=4, characteristic=1),
+                                                 all_cells=False)
+    b = oracle_mod.OracleMesh(m.xy, m.tri).setup(oracle_mod.params(order=4), all_cells=False)
+    fa, fla, _, _ = a.reconstruct_cells(U, [i])
+    fb, flb, _, _ = b.reconstruct_cells(U, [i])
+    # same arithmetic up to the order of summation
+    assert np.abs(fa - fb).max() <= 1e-14 * np.abs(fb).max()
+    assert (fla[0] == flb[0]).all()
+
+
+def test_char_has_no_frozen_selection_or_adjoint(oracle_mod):
+    m, om = mesh_and_oracle(oracle_mod, 8, 3, 3, characteristic=1)
+    U = inputs.smooth_wave(m)
+    with pytest.raises(Exception):
+        om.residual(U, frozen_flags=np.zeros(om.n_cell, np.uint16))
+    with pytest.raises(Exception):
+        om.vjp(U, np.zeros(om.n_cell, np.uint16), np.ones_like(U))
+    r = om.rk_step(U, om.dt(U))
+    assert r["flags"].shape == (3, 3, om.n_cell)
