@@ -62,7 +62,11 @@ typedef struct teno_params {
                      /* paper; default 0)                                     */
   int32_t reorder;   /* 1 = Morton order of cells (default), 0 = user order   */
   int32_t n_threads; /* host threads for set-up, 0 = hardware concurrency     */
-  int32_t reserved;
+  int32_t characteristic; /* 1: select in characteristic variables, edge by */
+                     /* edge (Sec. 2.3; eigenvectors of the flux Jacobian in */
+                     /* the edge normal at the cell mean): flags become one  */
+                     /* word per local edge, no frozen or adjoint calls, no  */
+                     /* batches; 0: conservative variables (default)         */
   double dk_prime;   /* CWENO: d_K = 1 - 1/dk_prime > 0 (paper: 1e4)          */
 } teno_params;
 
@@ -138,7 +142,10 @@ void teno_solver_destroy(teno_solver* s);
  * reconstruction with TENO selection (Sec. 2.2-3.3), rotated HLL flux at the
  * face Gauss points (Sec. 4), face-flux gather per cell.  flags (nullable):
  * output, bit 4v+3 = large stencil kept for variable v, bits 4v..4v+2 = small
- * stencil kept in the second selection step. */
+ * stencil kept in the second selection step.  With characteristic != 0 the
+ * flags are uint16_t[3][n_cell], word e for local edge e, v counting the
+ * characteristic variables (speeds u.n - c, u.n entropy, u.n shear,
+ * u.n + c). */
 int teno_residual(teno_solver* s, const double* U, double* R, uint16_t* flags, void* stream);
 
 /* Same residual with the selection frozen to `flags` (input). */
@@ -166,6 +173,7 @@ int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk,
 
 /* One full SSP-RK3 step in place on U using library-owned stage buffers.
  * flags3: nullable device uint16_t[3][n_cell] (out, or in when frozen != 0).
+ * (uint16_t[3][3][n_cell] with characteristic != 0, output only.)
  * stages: nullable device double[3][n_cell][4], receives the stage inputs
  * U^n, U^(1), U^(2) (what the adjoint needs).
  * face_states3: nullable device double[3][face_state_doubles] (teno_info);

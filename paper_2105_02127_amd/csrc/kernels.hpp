@@ -205,6 +205,8 @@ struct ReconArgs {
   double* __restrict__ fp;             // [3 nq][n_pad][4]
   uint16_t* flags;                     // out, or in when frozen
   const int32_t* __restrict__ user_of; // [n_pad]
+  const double* __restrict__ geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area
+  const int4* __restrict__ nbinfo;     // [n_pad]: .w bit 6+e set when the cell is edge e's L side
   DevDiag* diag;
   int n_cell, n_tiles, n_pad;
   int frozen, variant, fallback, power;
@@ -392,15 +394,275 @@ __host__ __device__ constexpr int stage_int4(int rows4, int ustride) {
   return slot_int4(rows4) + 2 * ustride;
 }
 
+// Selection of one variable from its stencils' coefficients, in two parts so
+// that the small stencils' part can run while the large stencil's rows
+// stream in.  Small part: TENO step two over the small stencils (Sec. 3.3)
+// and their mean, or the CWENO sums of alpha_k a^k and d_k a^k (Sec. 2.4).
+template <bool CW>
+struct SmallPart {
+  unsigned nsm = 0;  // kept small stencils (bit k)
+  int ties = 0;      // near ties among the small stencils' chi
+  double ssum = 0.0; // sum of their gammas (TENO) or alphas (CWENO)
+  double asm_[5];    // mean of the kept ones (TENO) or sum alpha_k a^k (CWENO)
+  double dsm[CW ? 5 : 1];  // CWENO: sum d_k a^k
+};
+
+// bcoef(k, l) and coef(k, l): coefficient l of small stencil k, read for
+// the indicators and for the combination (a caller may recompute it rather
+// than hold all fifteen values).  Both are called by all lanes of a cell
+// together, never under a lane-dependent condition.
+template <bool CW, class BCoef, class CCoef>
+__device__ __forceinline__ void small_part(const ReconArgs& a, bool frozen, unsigned nib_in,
+                                           BCoef&& bcoef, CCoef&& coef, SmallPart<CW>& sp) {
+  auto beta = [&](int k) {
+    double w[5];
+#pragma unroll
+    for (int l = 0; l < 5; ++l) w[l] = bcoef(k, l);
+    return quad_form(SmoothForm<2>::B.v, w);
+  };
+  sp.nsm = nib_in & 7u;
+  if (!CW && !frozen && a.variant == 0) {
+    const double g0 = gamma_k(beta(0), a.eps, a.power);
+    const double g1 = gamma_k(beta(1), a.eps, a.power);
+    const double g2 = gamma_k(beta(2), a.eps, a.power);
+    sp.ssum = (g0 + g1) + g2;
+    const double x0 = g0 / sp.ssum, x1 = g1 / sp.ssum, x2 = g2 / sp.ssum;
+    if (a.ct > 0.0) {
+      sp.ties += fabs(x0 / a.ct - 1.0) <= a.tie_rel;
+      sp.ties += fabs(x1 / a.ct - 1.0) <= a.tie_rel;
+      sp.ties += fabs(x2 / a.ct - 1.0) <= a.tie_rel;
+    }
+    sp.nsm = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
+  }
+  if constexpr (!CW) {
+    const unsigned nsm = sp.nsm;
+    const int cnt = (int)(nsm & 1u) + (int)((nsm >> 1) & 1u) + (int)((nsm >> 2) & 1u);
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      // read outside the lane-dependent conditions: a coefficient formed by
+      // quad broadcasts needs all four lanes of the cell active
+      const double c0 = coef(0, l), c1 = coef(1, l), c2 = coef(2, l);
+      double acc = 0.0;
+      if (nsm & 1u) acc += c0;
+      if (nsm & 2u) acc += c1;
+      if (nsm & 4u) acc += c2;
+      sp.asm_[l] = cnt > 0 ? acc / (double)cnt : 0.0;
+    }
+  } else {
+    // alpha_k = d_k / (beta_k + eps)^power of the small stencils; their
+    // shares of the combination are finished once the large stencil's
+    // weight is known
+    const double w0 = a.cw_ds * gamma_k(beta(0), a.eps, a.power);
+    const double w1 = a.cw_ds * gamma_k(beta(1), a.eps, a.power);
+    const double w2 = a.cw_ds * gamma_k(beta(2), a.eps, a.power);
+    sp.ssum = (w0 + w1) + w2;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const double c0 = coef(0, l), c1 = coef(1, l), c2 = coef(2, l);
+      sp.asm_[l] = (w0 * c0 + w1 * c1) + w2 * c2;
+      sp.dsm[l] = a.cw_ds * ((c0 + c1) + c2);
+    }
+  }
+}
+
+// Large part: TENO step one (Sec. 3.2) and the selected coefficients, or
+// the CWENO combination P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k.
+// ab gets the combined coefficients, nib the variable's 4-bit flag.
+template <int P, bool CW>
+__device__ __forceinline__ void large_part(const ReconArgs& a, bool frozen, unsigned nib_in,
+                                           const SmallPart<CW>& sp,
+                                           const double (&aK)[OrderT<P>::NU],
+                                           double (&ab)[OrderT<P>::NU], unsigned& nib, int& ties) {
+  using O = OrderT<P>;
+  constexpr int NU = O::NU;
+  if constexpr (CW) {
+    const double wK = a.cw_dK * gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
+    const double iS = 1.0 / (sp.ssum + wK);
+    const double cK = wK / a.cw_dK;
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+      ab[l] = l < 5 ? (cK * (aK[l] - sp.dsm[l]) + sp.asm_[l]) * iS : (cK * aK[l]) * iS;
+    nib = 0u;
+  } else {
+    bool keepK = true;
+    if (frozen) {
+      keepK = (nib_in & 8u) != 0;
+    } else if (a.variant == 0) {
+      const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
+      const double chiK = gK / (sp.ssum + gK);
+      if (a.ct > 0.0 && fabs(chiK / a.ct - 1.0) <= a.tie_rel) ++ties;
+      keepK = chiK >= a.ct;
+      if (!keepK) ties += sp.ties;
+    }
+    nib = keepK ? 8u : sp.nsm;
+#pragma unroll
+    for (int l = 0; l < NU; ++l) ab[l] = keepK ? aK[l] : (l < 5 ? sp.asm_[l] : 0.0);
+  }
+}
+
+// Characteristic projection of lane variable v (Sec. 2.3): row v of L
+// (char_lrow) and row v of R (char_rrow), where R's columns are the right
+// eigenvectors of the Euler flux Jacobian in direction (nx, ny) at the cell
+// mean u (quad lanes 0..3), for the speeds u.n - c, u.n (entropy), u.n
+// (shear), u.n + c, and L = R^-1 in closed form (b1 = (gamma-1)/c^2,
+// b2 = b1 |u|^2 / 2).  A mean that is not physical keeps the conservative
+// variables (identity rows).  The two are formed apart, each when needed,
+// to keep fewer registers live.
+struct CharState {
+  double ux, uy, q2, c, H, un, ut;
+};
+__device__ __forceinline__ CharState char_state(double u0, double nx, double ny, double g) {
+  const double rho = quad_bcast<0>(u0), mx = quad_bcast<1>(u0), my = quad_bcast<2>(u0),
+               en = quad_bcast<3>(u0);
+  CharState S;
+  const double ir = 1.0 / rho;
+  S.ux = mx * ir;
+  S.uy = my * ir;
+  S.q2 = S.ux * S.ux + S.uy * S.uy;
+  const double p = (g - 1.0) * (en - 0.5 * rho * S.q2);
+  S.c = sqrt(g * p * ir);
+  S.H = (en + p) * ir;
+  S.un = S.ux * nx + S.uy * ny;
+  S.ut = S.uy * nx - S.ux * ny;
+  return S;
+}
+
+__device__ __forceinline__ void char_lrow(double u0, double nx, double ny, double g, bool ok, int v,
+                                          double (&lrow)[4]) {
+  if (!ok) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lrow[j] = (j == v) ? 1.0 : 0.0;
+    return;
+  }
+  const CharState S = char_state(u0, nx, ny, g);
+  const double ic = 1.0 / S.c;
+  const double b1 = (g - 1.0) * ic * ic, b2 = 0.5 * S.q2 * b1;
+  const double L[4][4] = {
+      {0.5 * (b2 + S.un * ic), -0.5 * (b1 * S.ux + nx * ic), -0.5 * (b1 * S.uy + ny * ic), 0.5 * b1},
+      {1.0 - b2, b1 * S.ux, b1 * S.uy, -b1},
+      {-S.ut, -ny, nx, 0.0},
+      {0.5 * (b2 - S.un * ic), -0.5 * (b1 * S.ux - nx * ic), -0.5 * (b1 * S.uy - ny * ic), 0.5 * b1}};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) lrow[j] = pick4(L[0][j], L[1][j], L[2][j], L[3][j], v);
+}
+
+__device__ __forceinline__ void char_rrow(double u0, double nx, double ny, double g, bool ok, int v,
+                                          double (&rrow)[4]) {
+  if (!ok) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rrow[j] = (j == v) ? 1.0 : 0.0;
+    return;
+  }
+  const CharState S = char_state(u0, nx, ny, g);
+  const double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                          {S.ux - S.c * nx, S.ux, -ny, S.ux + S.c * nx},
+                          {S.uy - S.c * ny, S.uy, nx, S.uy + S.c * ny},
+                          {S.H - S.c * S.un, 0.5 * S.q2, S.ut, S.H + S.c * S.un}};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) rrow[j] = pick4(R[0][j], R[1][j], R[2][j], R[3][j], v);
+}
+
+// sum_j row[j] x_j, x_j = lane j's x of this cell's quad.  Operand and
+// result pass through opaque copies, which keep each product whole and in
+// order: the broadcasts of a coefficient are the same on every edge, and
+// left visible the compiler forms them all ahead of their use and holds
+// four copies of every coefficient across the edges.
+__device__ __forceinline__ double quad_dot(const double (&row)[4], double x) {
+  asm volatile("" : "+v"(x));
+  double s = row[0] * quad_bcast<0>(x);
+  s = fma(row[1], quad_bcast<1>(x), s);
+  s = fma(row[2], quad_bcast<2>(x), s);
+  s = fma(row[3], quad_bcast<3>(x), s);
+  asm volatile("" : "+v"(s));
+  return s;
+}
+
+// Characteristic-variable phase of one cell (Sec. 2.3), after the
+// least-squares phase: for each local edge, project the coefficients of
+// all four stencils onto the edge's characteristic variables (lane v:
+// variable v), select (or weight) per variable, evaluate at the edge's
+// Gauss points and map back.  Edges run one after another (a loop, not
+// unrolled) so that only one edge's projected coefficients are live; each
+// edge's states and flags are written as soon as they are known and
+// overwritten if the cell falls back to first order.
+template <int P, int NQ, bool CW>
+__device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as)[3][5],
+                                           const double (&aK)[OrderT<P>::NU], double u0, int cell,
+                                           bool live, bool writer, int g, int v) {
+  using O = OrderT<P>;
+  constexpr int NU = O::NU;
+  const bool avg_ok = physical(quad_bcast<0>(u0), quad_bcast<1>(u0), quad_bcast<2>(u0),
+                               quad_bcast<3>(u0), a.gamma);
+  const double* __restrict__ gc = a.geo + (size_t)(live ? cell : 0) * 10;
+  const int side = a.nbinfo[live ? cell : 0].w;  // face normals point out of the L side
+  int ties = 0;
+  bool fp_ok = true;
+  static_for<0, 3>([&](auto E) {
+    constexpr int e = E;
+    // one edge at a time: keeps the scheduler from overlapping the edges
+    __builtin_amdgcn_sched_barrier(0);
+    // outward unit normal of edge e
+    const double sg = ((side >> (6 + e)) & 1) ? 1.0 : -1.0;
+    const double nx = sg * gc[3 * e], ny = sg * gc[3 * e + 1];
+    double wK[NU], ab[NU];
+    SmallPart<CW> sp;
+    {
+      double lrow[4];
+      char_lrow(u0, nx, ny, a.gamma, avg_ok, v, lrow);
+#pragma unroll
+      for (int l = 0; l < NU; ++l) wK[l] = quad_dot(lrow, aK[l]);
+      auto proj = [&](int k, int l) { return quad_dot(lrow, as[k][l]); };
+      small_part<CW>(a, false, 8u, proj, proj, sp);
+    }
+    unsigned nib = 0u;
+    large_part<P, CW>(a, false, 8u, sp, wK, ab, nib, ties);
+    double rrow[4];
+    char_rrow(u0, nx, ny, a.gamma, avg_ok, v, rrow);
+    const double* __restrict__ fb = &FaceBasis<O::R, NQ>::P.v[e * NQ][0];
+#pragma unroll
+    for (int kq = 0; kq < NQ; ++kq) {
+      double dw = 0.0;
+#pragma unroll
+      for (int l = 0; l < NU; ++l) dw = fma(ab[l], fb[kq * NU + l], dw);
+      const double val = u0 + quad_dot(rrow, dw);
+      fp_ok = fp_ok && physical(quad_bcast<0>(val), quad_bcast<1>(val), quad_bcast<2>(val),
+                                quad_bcast<3>(val), a.gamma);
+      if (live && writer) a.fp[((size_t)(e * NQ + kq) * a.n_pad + cell) * 4 + v] = val;
+    }
+    if (a.flags) {  // one word per local edge: flags[e][n_cell]
+      unsigned f = nib << (4 * v);
+      f |= __shfl_xor(f, 1);
+      f |= __shfl_xor(f, 2);
+      if (live && g == 0) a.flags[(size_t)e * a.n_cell + cell] = (uint16_t)f;
+    }
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- non-physical states (all four lanes of a cell agree) ----
+  if (live && g == 0 && !(avg_ok && fp_ok)) {
+    atomicAdd(&a.diag->nonphysical, 1ull);
+    atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
+  }
+  if (!fp_ok && avg_ok && a.fallback) {
+    if (live && writer)
+      for (int q = 0; q < 3 * NQ; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + v] = u0;
+    if (a.flags && live && g == 0)
+      for (int e = 0; e < 3; ++e) a.flags[(size_t)e * a.n_cell + cell] = 0;
+    if (live && g == 0) atomicAdd(&a.diag->fallbacks, 1ull);
+  }
+  if (live && writer && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
+}
+
 // Reconstruction of one tile of kTile cells by one wavefront; `stage` is
 // this wavefront's LDS area (stage_int4(ROWS4, a.ustride) int4).  CW selects the
-// CWENO weighting (Sec. 2.4) instead of the TENO selection (Sec. 3).
-template <int P, int NQ, bool CW = false>
+// CWENO weighting (Sec. 2.4) instead of the TENO selection (Sec. 3); CH
+// selects in characteristic variables, edge by edge (Sec. 2.3).
+template <int P, int NQ, bool CW = false, bool CH = false>
 __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, int lane,
                                                  int4* stage) {
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
+  static_assert(!CH || kLanesPerCell == 4, "the projection shares values within a quad");
   // stage this tile's member slots ([row4][cell][4] uint16) and the states
   // of its distinct stencil members in LDS
   wave_lds_sync();  // earlier readers of `stage` are done
@@ -457,48 +719,10 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
     ls.prime();
     static_for<0, 5>([&](auto L) { as[2][L] = S2::template coef<L>(sk2, v, lane); });
   }
-  unsigned nsm = nib_in & 7u;
-  int ties_small = 0;
-  double ssum = 0.0;
-  if (!frozen && a.variant == 0) {
-    const double g0 = gamma_k(quad_form(SmoothForm<2>::B.v, as[0]), a.eps, a.power);
-    const double g1 = gamma_k(quad_form(SmoothForm<2>::B.v, as[1]), a.eps, a.power);
-    const double g2 = gamma_k(quad_form(SmoothForm<2>::B.v, as[2]), a.eps, a.power);
-    ssum = (g0 + g1) + g2;
-    const double x0 = g0 / ssum, x1 = g1 / ssum, x2 = g2 / ssum;
-    if (a.ct > 0.0) {
-      ties_small += fabs(x0 / a.ct - 1.0) <= a.tie_rel;
-      ties_small += fabs(x1 / a.ct - 1.0) <= a.tie_rel;
-      ties_small += fabs(x2 / a.ct - 1.0) <= a.tie_rel;
-    }
-    nsm = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
-  }
-  double asm_[5];
-  if constexpr (!CW) {
-    const int cnt = (int)(nsm & 1u) + (int)((nsm >> 1) & 1u) + (int)((nsm >> 2) & 1u);
-#pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      double acc = 0.0;
-      if (nsm & 1u) acc += as[0][l];
-      if (nsm & 2u) acc += as[1][l];
-      if (nsm & 4u) acc += as[2][l];
-      asm_[l] = cnt > 0 ? acc / (double)cnt : 0.0;
-    }
-  }
-  // CWENO: alpha_k = d_k / (beta_k + eps)^power of the small stencils, with
-  // asm_ = sum_k alpha_k a^k and dsm = sum_k d_k a^k (their shares of the
-  // combination, finished once the large stencil's weight is known)
-  double dsm[CW ? 5 : 1];
-  if constexpr (CW) {
-    const double w0 = a.cw_ds * gamma_k(quad_form(SmoothForm<2>::B.v, as[0]), a.eps, a.power);
-    const double w1 = a.cw_ds * gamma_k(quad_form(SmoothForm<2>::B.v, as[1]), a.eps, a.power);
-    const double w2 = a.cw_ds * gamma_k(quad_form(SmoothForm<2>::B.v, as[2]), a.eps, a.power);
-    ssum = (w0 + w1) + w2;
-#pragma unroll
-    for (int l = 0; l < 5; ++l) {
-      asm_[l] = (w0 * as[0][l] + w1 * as[1][l]) + w2 * as[2][l];
-      dsm[l] = a.cw_ds * ((as[0][l] + as[1][l]) + as[2][l]);
-    }
+  SmallPart<CW> sp;
+  if constexpr (!CH) {
+    auto c = [&](int k, int l) { return as[k][l]; };
+    small_part<CW>(a, frozen, nib_in, c, c, sp);
   }
 
   // ---- large stencil (rows 33.., entries 165..) ----
@@ -508,38 +732,24 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
     ls.run(sk);
     static_for<0, NU>([&](auto L) { aK[L] = LargeS::template coef<L>(sk, v, lane); });
   }
-  bool keepK = true;
-  int ties = 0;
-  if constexpr (CW) {
-    // P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k, w = alpha / sum alpha
-    const double wK = a.cw_dK * gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
-    const double iS = 1.0 / (ssum + wK);
-    const double cK = wK / a.cw_dK;
-#pragma unroll
-    for (int l = 0; l < NU; ++l)
-      aK[l] = l < 5 ? (cK * (aK[l] - dsm[l]) + asm_[l]) * iS : (cK * aK[l]) * iS;
-  } else if (frozen) {
-    keepK = (nib_in & 8u) != 0;
-  } else if (a.variant == 0) {
-    const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
-    const double chiK = gK / (ssum + gK);
-    if (a.ct > 0.0 && fabs(chiK / a.ct - 1.0) <= a.tie_rel) ++ties;
-    keepK = chiK >= a.ct;
-    if (!keepK) ties += ties_small;
+  if constexpr (CH) {
+    char_edges<P, NQ, CW>(a, as, aK, u0, cell, live, writer, g, v);
+    return;
   }
-  unsigned nib = CW ? 0u : (keepK ? 8u : nsm);
-  double ab[NU];
-#pragma unroll
-  for (int l = 0; l < NU; ++l) ab[l] = keepK ? aK[l] : (l < 5 ? asm_[l] : 0.0);
-
-  // ---- face Gauss points (variable v of this cell) ----
+  int ties = 0;
+  unsigned nib = 0u;
   double val[NP];
+  {
+    double ab[NU];
+    large_part<P, CW>(a, frozen, nib_in, sp, aK, ab, nib, ties);
+    // ---- face Gauss points (variable v of this cell) ----
 #pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    double s = u0;
+    for (int q = 0; q < NP; ++q) {
+      double s = u0;
 #pragma unroll
-    for (int l = 0; l < NU; ++l) s = fma(ab[l], FaceBasis<O::R, NQ>::P.v[q][l], s);
-    val[q] = s;
+      for (int l = 0; l < NU; ++l) s = fma(ab[l], FaceBasis<O::R, NQ>::P.v[q][l], s);
+      val[q] = s;
+    }
   }
   // ---- non-physical states (all four lanes of a cell agree) ----
   if (!frozen) {
@@ -580,7 +790,27 @@ __global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
-  reconstruct_tile<P, NQ, CW>(a, tile, lane, lds + wave * a.lds_stride);
+  reconstruct_tile<P, NQ, CW, false>(a, tile, lane, lds + wave * a.lds_stride);
+}
+
+// The same in characteristic variables.  The per-edge phase holds the
+// conservative and the projected coefficients at once; the register budget
+// is capped at TENO_CHAR_WAVES_PER_EU wavefronts per SIMD.
+#ifndef TENO_CHAR_WAVES_PER_EU
+#define TENO_CHAR_WAVES_PER_EU 0
+#endif
+#if TENO_CHAR_WAVES_PER_EU > 0
+#define TENO_CHAR_ATTR __attribute__((amdgpu_waves_per_eu(TENO_CHAR_WAVES_PER_EU)))
+#else
+#define TENO_CHAR_ATTR
+#endif
+template <int P, int NQ, bool CW>
+__global__ __launch_bounds__(256) TENO_CHAR_ATTR void k_reconstruct_char(ReconArgs a) {
+  extern __shared__ int4 lds[];  // 4 wavefronts x a.lds_stride
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= a.n_tiles) return;  // whole wavefront leaves together
+  reconstruct_tile<P, NQ, CW, true>(a, tile, lane, lds + wave * a.lds_stride);
 }
 
 // ---------------------------------------------------------------------------

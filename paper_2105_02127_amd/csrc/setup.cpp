@@ -433,6 +433,8 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   if (p.order < 3 || p.order > 6) return fail(TENO_EARG, "order must be 3..6");
   if (p.variant < 0 || p.variant > 2) return fail(TENO_EARG, "variant must be 0, 1 or 2");
   if (p.variant == 2 && !(p.dk_prime > 1.0)) return fail(TENO_EARG, "CWENO needs dk_prime > 1");
+  if (p.characteristic != 0 && p.characteristic != 1)
+    return fail(TENO_EARG, "characteristic must be 0 or 1");
   if (!(p.ct >= 0.0 && p.ct <= 1.0 / 3.0)) return fail(TENO_EARG, "C_T must lie in [0, 1/3]");
   if (p.power < 1 || p.power > 16) return fail(TENO_EARG, "power must be 1..16");
   if (p.n_quad != 0 && (p.n_quad < 2 || p.n_quad > 3)) return fail(TENO_EARG, "n_quad must be 0, 2 or 3");

@@ -177,6 +177,8 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   a.fp = fp ? fp : s->fp;
   a.flags = flags;
   a.user_of = s->user_of;
+  a.geo = s->geo;
+  a.nbinfo = s->nbinfo;
   a.diag = s->diag;
   a.n_cell = s->n_cell;
   a.n_tiles = s->n_tiles;
@@ -193,16 +195,19 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   a.cw_ds = (1.0 - a.cw_dK) / 3.0;
   const int blocks = (s->n_tiles + 3) / 4;
   const size_t lds = (size_t)4 * a.lds_stride * sizeof(int4);
-  const bool cw = s->prm.variant == 2;
+  const bool cw = s->prm.variant == 2, ch = s->prm.characteristic != 0;
   int rc = TENO_OK;
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
+    constexpr int p = decltype(P)::value, nq = decltype(NQ)::value;
     rc = timed(s, 0, st, [&]() {
-      if (cw)
-        hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value, true>),
-                           dim3(blocks), dim3(256), lds, st, a);
+      if (ch && cw)
+        hipLaunchKernelGGL((k_reconstruct_char<p, nq, true>), dim3(blocks), dim3(256), lds, st, a);
+      else if (ch)
+        hipLaunchKernelGGL((k_reconstruct_char<p, nq, false>), dim3(blocks), dim3(256), lds, st, a);
+      else if (cw)
+        hipLaunchKernelGGL((k_reconstruct<p, nq, true>), dim3(blocks), dim3(256), lds, st, a);
       else
-        hipLaunchKernelGGL((k_reconstruct<decltype(P)::value, decltype(NQ)::value, false>),
-                           dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_reconstruct<p, nq, false>), dim3(blocks), dim3(256), lds, st, a);
     });
   });
   return rc;
@@ -316,10 +321,13 @@ int check_solver(teno_solver* s) {
   return TENO_OK;
 }
 
-// CWENO (variant 2) has no selection to freeze and hence no adjoint.
+// CWENO (variant 2) has no selection to freeze and hence no adjoint; the
+// frozen and adjoint paths work in conservative variables only.
 int needs_selection(const teno_solver* s, const char* what) {
   if (s->prm.variant == 2)
     return fail(TENO_EARG, std::string(what) + " needs a stencil selection (TENO or LINEAR), not CWENO");
+  if (s->prm.characteristic)
+    return fail(TENO_EARG, std::string(what) + " works in conservative variables only");
   return TENO_OK;
 }
 
@@ -603,7 +611,8 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
   hipStream_t st = (hipStream_t)stream;
   const size_t n = (size_t)s->n_cell;
   const size_t nb = n * 4 * sizeof(double);
-  auto fl = [&](int k) { return flags3 ? flags3 + (size_t)k * n : nullptr; };
+  const size_t nfl = n * (s->prm.characteristic ? 3 : 1);  // flag words per stage
+  auto fl = [&](int k) { return flags3 ? flags3 + (size_t)k * nfl : nullptr; };
   const size_t fsz = face_state_doubles(s);
   auto fs = [&](int k) { return face_states3 ? face_states3 + (size_t)k * fsz : nullptr; };
   if (stages) {
@@ -931,6 +940,8 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
       a.fp = s->fp;
       a.flags = nullptr;
       a.user_of = s->user_of;
+      a.geo = s->geo;
+      a.nbinfo = s->nbinfo;
       a.diag = s->diag;
       a.n_cell = s->n_cell;
       a.n_tiles = s->n_tiles;
@@ -1029,6 +1040,8 @@ int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out) 
     for (int k = 0; k < m; ++k)
       if (solvers[k] == solvers[m]) return fail(TENO_EARG, "a solver appears twice in the batch");
     if (solvers[m]->prm.variant == 2) return fail(TENO_EARG, "CWENO meshes cannot be batched");
+    if (solvers[m]->prm.characteristic)
+      return fail(TENO_EARG, "meshes in characteristic variables cannot be batched");
   }
   DeviceScope ds(solvers[0]->device);
   teno_batch* b = new (std::nothrow) teno_batch();

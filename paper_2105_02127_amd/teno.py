@@ -22,7 +22,7 @@ class Params(C.Structure):
     _fields_ = [("order", C.c_int32), ("n_quad", C.c_int32), ("variant", C.c_int32),
                 ("power", C.c_int32), ("ct", C.c_double), ("eps", C.c_double),
                 ("gamma", C.c_double), ("tie_rel", C.c_double), ("fallback", C.c_int32),
-                ("reorder", C.c_int32), ("n_threads", C.c_int32), ("reserved", C.c_int32),
+                ("reorder", C.c_int32), ("n_threads", C.c_int32), ("characteristic", C.c_int32),
                 ("dk_prime", C.c_double)]
 
 
@@ -247,6 +247,9 @@ class Solver:
         self.n_quad = info.n_quad
         self.order = info.order
         self.face_state_doubles = int(info.face_state_doubles)
+        # flag words per cell: one, or one per local edge in characteristic
+        # variables
+        self.flag_words = 3 if mesh.params.characteristic else 1
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -258,11 +261,14 @@ class Solver:
         import torch
         return _ptr(t, (self.n_cell, 4), torch.float64, name, nullable)
 
+    def _flag_shape(self, n):
+        base = (self.n_cell,) if self.flag_words == 1 else (self.flag_words, self.n_cell)
+        return base if n == 1 else (n,) + base
+
     def _flags(self, t, n=1, name="flags", nullable=True):
         import torch
-        shape = (self.n_cell,) if n == 1 else (n, self.n_cell)
         # uint16 bit patterns carried in int16 tensors (view as uint16 on the host)
-        return _ptr(t, shape, torch.int16, name, nullable)
+        return _ptr(t, self._flag_shape(n), torch.int16, name, nullable)
 
     def _dt(self, t):
         import torch
@@ -274,8 +280,7 @@ class Solver:
 
     def empty_flags(self, n=1):
         import torch
-        shape = (self.n_cell,) if n == 1 else (n, self.n_cell)
-        return torch.zeros(shape, dtype=torch.int16, device=f"cuda:{self.device}")
+        return torch.zeros(self._flag_shape(n), dtype=torch.int16, device=f"cuda:{self.device}")
 
     # -- calls --
     def residual(self, U, R=None, flags=None, stream=None):

@@ -100,3 +100,12 @@ def test_cweno_meshes_are_not_batched(torch_cuda):
     s = teno.Solver(teno.Mesh(m.xy, m.tri).setup(order=4, variant=2))
     with pytest.raises(teno.TenoError):
         Batch([s])
+
+
+def test_characteristic_meshes_are_not_batched(torch_cuda):
+    from paper_2105_02127_amd import teno
+    from paper_2105_02127_amd.batch import Batch
+    m = inputs.jittered_periodic_mesh(12, 509)
+    s = teno.Solver(teno.Mesh(m.xy, m.tri).setup(order=4, characteristic=1))
+    with pytest.raises(teno.TenoError):
+        Batch([s])

@@ -41,16 +41,18 @@ class Case:
     """One mesh + state on both sides (oracle in user order, GPU internal)."""
 
     def __init__(self, teno, oracle_mod, torch, n, seed, order, ic="random_lines", fallback=1,
-                 oracle_all=True, variant=0):
-        print(f"[case] n={n} seed={seed} order={order} ic={ic} fallback={fallback}", flush=True)
+                 oracle_all=True, variant=0, characteristic=0):
+        print(f"[case] n={n} seed={seed} order={order} ic={ic} fallback={fallback} "
+              f"variant={variant} characteristic={characteristic}", flush=True)
         self.m = inputs.jittered_periodic_mesh(n, seed)
         self.U = inputs.make_state(self.m, ic)
         self.lm = teno.Mesh(self.m.xy, self.m.tri).setup(order=order, fallback=fallback,
-                                                         variant=variant)
+                                                         variant=variant,
+                                                         characteristic=characteristic)
         self.sv = teno.Solver(self.lm)
         self.om = oracle_mod.OracleMesh(self.m.xy, self.m.tri)
-        self.om.setup(oracle_mod.params(order=order, fallback=fallback, variant=variant),
-                      all_cells=oracle_all)
+        self.om.setup(oracle_mod.params(order=order, fallback=fallback, variant=variant,
+                                        characteristic=characteristic), all_cells=oracle_all)
         self.perm = self.lm.perm
         self.torch = torch
         self.Ud = torch.as_tensor(self.U[self.perm], device="cuda")
@@ -65,7 +67,12 @@ class Case:
         return out
 
     def flags_user(self, t):
-        return self.host_user(t).view(np.uint16)
+        """Flags in user cell order; [..., n_cell] layouts keep their
+        leading axes (one word per local edge in characteristic variables)."""
+        a = t.cpu().numpy().view(np.uint16)
+        out = np.empty_like(a)
+        out[..., self.perm] = a
+        return out
 
     def flux_scale(self):
         area, _, _ = self.om.geometry()
@@ -157,6 +164,71 @@ def test_cweno_matches_oracle(teno, oracle_mod, torch_cuda, order, ic):
         c.sv.vjp_residual(c.Ud, flags, c.Ud)
     with pytest.raises(teno.TenoError):
         c.sv.residual_frozen(c.Ud, flags)
+
+
+@pytest.mark.parametrize("order,variant,ic", [(3, 0, "random_lines"), (4, 0, "random_lines"),
+                                               (5, 0, "random_lines"), (6, 0, "wave_plus_jump"),
+                                               (5, 2, "random_lines"), (4, 1, "random_lines")])
+def test_characteristic_matches_oracle(teno, oracle_mod, torch_cuda, order, variant, ic):
+    # selection in characteristic variables, edge by edge (Sec. 2.3): face
+    # states, per-edge flags, residual and an RK step with its flags
+    torch = torch_cuda
+    c = Case(teno, oracle_mod, torch, 17, 90 + order, order, ic=ic, variant=variant,
+             characteristic=1)
+    ores = c.om.residual(c.U, want_fp=True)
+    flags = c.sv.empty_flags()
+    assert tuple(flags.shape) == (3, c.m.n_cell)
+    fs = c.sv.reconstruct(c.Ud, flags=flags)
+    R = c.sv.residual(c.Ud)
+    torch.cuda.synchronize()
+    fs_user = np.empty((c.m.n_cell, fs.shape[0], 4))
+    fs_user[c.perm] = fs.permute(1, 0, 2).cpu().numpy()
+    assert_states(fs_user, ores["fp"].reshape(c.m.n_cell, -1, 4), what="characteristic face states")
+    gfl = c.flags_user(flags)
+    assert flag_mismatch(gfl, ores["flags"]) <= ores["diag"]["near_ties"]
+    if variant == 0:
+        assert (ores["flags"] != 0x8888).any()     # the case exercises the selection
+    assert np.abs(c.host_user(R) - ores["R"]).max() <= REL * c.flux_scale()
+    dto = c.om.dt(c.U, 0.4)
+    dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
+    ref = c.om.rk_step(c.U, dto)
+    Ud = c.Ud.clone()
+    fl3 = c.sv.empty_flags(3)
+    assert tuple(fl3.shape) == (3, 3, c.m.n_cell)
+    c.sv.rk_step(Ud, dt, flags3=fl3)
+    torch.cuda.synchronize()
+    assert_states(c.host_user(Ud), ref["U"], what="characteristic U^{n+1}")
+    assert flag_mismatch(c.flags_user(fl3), ref["flags"]) <= ref["diag"]["near_ties"]
+    # the frozen and adjoint paths work in conservative variables only
+    with pytest.raises(teno.TenoError):
+        c.sv.residual_frozen(c.Ud, flags)
+    with pytest.raises(teno.TenoError):
+        c.sv.vjp_residual(c.Ud, flags, c.Ud)
+
+
+def test_characteristic_contact_keeps_velocity_and_pressure(teno, oracle_mod, torch_cuda):
+    # a contact lies in the entropy field only: the face states keep the
+    # uniform velocity and pressure, and only that field drops stencils
+    torch = torch_cuda
+    m = inputs.jittered_periodic_mesh(24, 95)
+    cen = m.xy[m.tri].mean(1)
+    rho = np.where(np.sin(2 * np.pi * (cen[:, 0] + 0.3 * cen[:, 1])) > 0, 3.0, 1.0)
+    rho = rho + 0.2 * np.cos(2 * np.pi * cen[:, 1])
+    vx, vy, p = 0.7, -0.3, 1.0
+    U = np.stack([rho, rho * vx, rho * vy, p / 0.4 + 0.5 * rho * (vx * vx + vy * vy)], 1)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=5, characteristic=1)
+    sv = teno.Solver(lm)
+    Ud = torch.as_tensor(U[lm.perm], device="cuda")
+    flags = sv.empty_flags()
+    fs = sv.reconstruct(Ud, flags=flags).cpu().numpy()
+    fl = flags.cpu().numpy().view(np.uint16)
+    ux, uy = fs[..., 1] / fs[..., 0], fs[..., 2] / fs[..., 0]
+    pf = 0.4 * (fs[..., 3] - 0.5 * fs[..., 0] * (ux * ux + uy * uy))
+    assert np.abs(ux - vx).max() < 1e-12 and np.abs(uy - vy).max() < 1e-12
+    assert np.abs(pf - p).max() < 1e-12
+    assert ((fl >> 4) & 0xF != 8).any()
+    for v in (0, 2, 3):
+        assert ((fl >> (4 * v)) & 0xF == 8).all()
 
 
 def test_smooth_wave_all_large_stencil(teno, oracle_mod, torch_cuda):
@@ -330,14 +402,15 @@ def test_vjp_rk_step_matches_oracle(teno, oracle_mod, torch_cuda):
 # --------------------------------------------------------------------------
 # full-size workloads: sampled cells the oracle computes one by one
 # --------------------------------------------------------------------------
-def _sampled(teno, oracle_mod, torch, key, n_sample=160):
+def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0):
     w, m, U = inputs.make_workload(key)
-    print(f"[full-size] {w['name']} cells={m.n_cell}", flush=True)
-    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1)
+    print(f"[full-size] {w['name']} cells={m.n_cell} characteristic={characteristic}", flush=True)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1, characteristic=characteristic)
     sv = teno.Solver(lm)
     perm = lm.perm
     om = oracle_mod.OracleMesh(m.xy, m.tri)
-    om.setup(oracle_mod.params(order=w["order"], fallback=1), all_cells=False)
+    om.setup(oracle_mod.params(order=w["order"], fallback=1, characteristic=characteristic),
+             all_cells=False)
     rng = np.random.default_rng(key)
     cells = np.unique(np.concatenate([rng.integers(0, m.n_cell, n_sample),
                                       perm[-5:], perm[:3]]))       # include the ragged tail
@@ -351,7 +424,9 @@ def _sampled(teno, oracle_mod, torch, key, n_sample=160):
     fp, ofl, _, odg = om.reconstruct_cells(U, cells)
     got = fs[:, torch.as_tensor(inv[cells], device="cuda")].permute(1, 0, 2).cpu().numpy()
     assert_states(got, fp.reshape(len(cells), -1, 4), what="face states")
-    gfl = flags.cpu().numpy().view(np.uint16)[inv[cells]]
+    gfl = flags.cpu().numpy().view(np.uint16)[..., inv[cells]]
+    if characteristic:
+        gfl = gfl.T                                   # [cell][edge] like the oracle's
     assert flag_mismatch(gfl, ofl) <= odg["near_ties"]
     Ro, _ = om.residual_cells(U, cells)
     Rg = R.cpu().numpy()[inv[cells]]
@@ -391,3 +466,8 @@ def test_full_size_teno6_wavejump_sampled(teno, oracle_mod, torch_cuda):
 def test_full_size_teno5_khi_sampled(teno, oracle_mod, torch_cuda):
     # the paper's KHI state (Sec. 5.8) on 576,738 cells
     _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=96)
+
+
+def test_full_size_teno5_khi_characteristic_sampled(teno, oracle_mod, torch_cuda):
+    # characteristic variables on the KHI workload at full size
+    _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=64, characteristic=1)

@@ -115,6 +115,20 @@ def test_mesh_errors(teno):
     # without the periodic wrap a planar mesh has boundary (or folded) edges
     with pytest.raises(teno.TenoError, match="open edge|non-manifold"):
         teno.Mesh(m.xy, m.tri, period=None)
+    with pytest.raises(teno.TenoError, match="characteristic"):
+        teno.Mesh(m.xy, m.tri).setup(order=3, characteristic=2)
+
+
+def test_tile_member_limit(teno):
+    # 16 consecutive cells share one LDS list of distinct stencil members; a
+    # shuffled cell order kept as given (reorder=0) scatters the tiles past
+    # the limit, and the default reordering keeps them well inside it
+    m = inputs.jittered_periodic_mesh(20, 8)
+    rng = np.random.default_rng(0)
+    tri = m.tri[rng.permutation(m.n_cell)]
+    with pytest.raises(teno.TenoError, match="distinct stencil members"):
+        teno.Mesh(m.xy, tri).setup(order=6, reorder=0)
+    teno.Mesh(m.xy, tri).setup(order=6)
 
 
 def test_orientation_fix_matches_oracle(teno, oracle_mod):
