@@ -68,6 +68,9 @@ def lib():
         L.oracle_basis.argtypes = [C.c_int, ip, ip, dp]
         L.oracle_select.argtypes = [C.POINTER(Params), dp, dp, ip]
         L.oracle_hll.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, dp]
+        L.oracle_boundary_count.argtypes = [vp]
+        L.oracle_boundary_faces.argtypes = [vp, ip, ip]
+        L.oracle_set_boundary.argtypes = [vp, ip, dp]
         L.oracle_char_basis.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.oracle_cweno_weights.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.oracle_reconstruct_cells.argtypes = [vp, dp, C.c_int, ip, dp, up, dp, C.POINTER(Diag)]
@@ -174,6 +177,21 @@ class OracleMesh:
         cf = np.empty((self.n_cell, 3), dtype=np.int32)
         lib().oracle_mesh_faces(self.h, _i(fL), _i(fR), _i(fLe), _i(fRe), _d(n), _d(ln), _i(cf))
         return dict(L=fL, R=fR, Le=fLe, Re=fRe, normal=n, length=ln, cell_face=cf)
+
+    # boundaries -----------------------------------------------------------
+    def boundary_faces(self):
+        """(verts [nb, 2], cell [nb]) of the boundary faces (open axes)."""
+        nb = int(lib().oracle_boundary_count(self.h))
+        v = np.empty((nb, 2), dtype=np.int32)
+        c = np.empty(nb, dtype=np.int32)
+        lib().oracle_boundary_faces(self.h, _i(v), _i(c))
+        return v, c
+
+    def set_boundary(self, kind, state=None):
+        k = np.ascontiguousarray(kind, dtype=np.int32)
+        st = None if state is None else _f64(state)
+        _check(lib().oracle_set_boundary(self.h, _i(k), None if st is None else _d(st)))
+        return self
 
     # setup ----------------------------------------------------------------
     def setup(self, prm: Params, all_cells: bool = True):

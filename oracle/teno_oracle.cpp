@@ -290,8 +290,8 @@ struct CellData {
 
 struct Mesh {
   int nv = 0, nc = 0, nf = 0;
-  bool periodic = false;
-  double P[2] = {0.0, 0.0};
+  bool periodic = false;              // both axes periodic
+  double P[2] = {0.0, 0.0};           // period per axis; 0: open axis
   std::vector<double> xy;
   std::vector<int> tri;
   std::vector<double> X;              // [nc][3][2] unwrapped about v0
@@ -299,6 +299,11 @@ struct Mesh {
   std::vector<int> fL, fR, fLe, fRe;  // face -> cells, local edges
   std::vector<double> fn, flen;       // face unit normal (out of L), length
   std::vector<int> cf;                // [nc][3] face of each local edge
+  // boundary faces (open axes): fR = fRe = -1; numbered by the (first,
+  // second) vertex of the face in its cell's counter-clockwise order
+  std::vector<int> bface, bidx;       // [nb] face; [nf] index or -1
+  std::vector<int> bkind;             // [nb] 1 transmissive, 2 reflective, 3 prescribed
+  std::vector<double> bstate;         // [nb][4]
   // reconstruction setup
   bool have_params = false;
   oracle_params prm{};
@@ -313,9 +318,8 @@ struct Mesh {
 };
 
 void min_image(const Mesh& m, double& dx, double& dy) {
-  if (!m.periodic) return;
-  dx -= m.P[0] * std::nearbyint(dx / m.P[0]);
-  dy -= m.P[1] * std::nearbyint(dy / m.P[1]);
+  if (m.P[0] > 0.0) dx -= m.P[0] * std::nearbyint(dx / m.P[0]);
+  if (m.P[1] > 0.0) dy -= m.P[1] * std::nearbyint(dy / m.P[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,30 +354,39 @@ void disp(const Mesh& m, int i, int j, double& dx, double& dy, double* sx = null
   dx = m.cen[2 * j] - m.cen[2 * i];
   dy = m.cen[2 * j + 1] - m.cen[2 * i + 1];
   double kx = 0.0, ky = 0.0;
-  if (m.periodic) {
+  if (m.P[0] > 0.0) {
     kx = std::nearbyint(dx / m.P[0]);
-    ky = std::nearbyint(dy / m.P[1]);
     dx -= m.P[0] * kx;
+  }
+  if (m.P[1] > 0.0) {
+    ky = std::nearbyint(dy / m.P[1]);
     dy -= m.P[1] * ky;
   }
   if (sx) *sx = -m.P[0] * kx;
   if (sy) *sy = -m.P[1] * ky;
 }
 
+// Reading for meshes with boundaries: a directional stencil whose cone holds
+// fewer than `want` cells is completed with the nearest cells outside it.
 bool stencil_brute(const Mesh& m, int i, int k, int want, std::vector<int>& out) {
-  std::vector<Cand> c;
+  std::vector<Cand> c, rest;
   for (int j = 0; j < m.nc; ++j) {
     if (j == i) continue;
     double dx, dy;
     disp(m, i, j, dx, dy);
-    if (!in_cone(m, i, k, dx, dy)) continue;
-    c.push_back({dx * dx + dy * dy, j});
+    if (in_cone(m, i, k, dx, dy))
+      c.push_back({dx * dx + dy * dy, j});
+    else
+      rest.push_back({dx * dx + dy * dy, j});
   }
-  if ((int)c.size() < want) return false;
   std::sort(c.begin(), c.end());
   out.clear();
-  for (int s = 0; s < want; ++s) out.push_back(c[s].id);
-  return true;
+  for (int s = 0; s < want && s < (int)c.size(); ++s) out.push_back(c[s].id);
+  if ((int)out.size() < want && !m.periodic) {
+    std::sort(rest.begin(), rest.end());
+    for (size_t s = 0; s < rest.size() && (int)out.size() < want; ++s) out.push_back(rest[s].id);
+  }
+  return (int)out.size() == want;
 }
 
 void build_bins(Mesh& m) {
@@ -468,8 +481,9 @@ bool build_cell(Mesh& m, int i, std::string& err) {
       int j = S.cells[s];
       double dx, dy, ox, oy;
       disp(m, i, j, dx, dy, &ox, &oy);
-      // members must stay within 0.4 period of the target along each axis
-      if (m.periodic && (std::fabs(dx) > 0.4 * m.P[0] || std::fabs(dy) > 0.4 * m.P[1])) {
+      // members must stay within 0.4 period of the target along each periodic axis
+      if ((m.P[0] > 0.0 && std::fabs(dx) > 0.4 * m.P[0]) ||
+          (m.P[1] > 0.0 && std::fabs(dy) > 0.4 * m.P[1])) {
         err = "mesh too small for the stencil (member beyond 0.4 period) at cell " +
               std::to_string(i);
         return false;
@@ -967,6 +981,26 @@ void hll_flux(const T* uL, const T* uR, double nx, double ny, double g, T* out) 
 // ---------------------------------------------------------------------------
 // Full residual (Sec. 2.1): R_i = -(1/|V_i|) sum_faces s_if Phi_f
 // ---------------------------------------------------------------------------
+// Outer state of boundary face b (normal n out of the domain) for the
+// Riemann problem at a Gauss point: transmissive copies the inner state,
+// reflective mirrors its velocity in the face, prescribed takes the given
+// state.
+template <class T>
+void boundary_state(const Mesh& m, int b, const T* uL, double nx, double ny, T* uR) {
+  if (m.bkind[b] == 3) {
+    for (int c = 0; c < 4; ++c) uR[c] = T(m.bstate[4 * (size_t)b + c]);
+  } else if (m.bkind[b] == 2) {
+    // momentum (mn, mt) in the face frame -> (-mn, mt)
+    T mn = uL[1] * nx + uL[2] * ny, mt = -uL[1] * ny + uL[2] * nx;
+    uR[0] = uL[0];
+    uR[1] = -mn * nx - mt * ny;
+    uR[2] = -mn * ny + mt * nx;
+    uR[3] = uL[3];
+  } else {
+    for (int c = 0; c < 4; ++c) uR[c] = uL[c];
+  }
+}
+
 template <class T>
 void face_flux(const Mesh& m, int f, const T* fp, T* phi) {
   const int nq = m.nq;
@@ -974,7 +1008,12 @@ void face_flux(const Mesh& m, int f, const T* fp, T* phi) {
   for (int c = 0; c < 4; ++c) phi[c] = T(0.0);
   for (int k = 0; k < nq; ++k) {
     const T* uL = &fp[((size_t)L * 3 * nq + eL * nq + k) * 4];
-    const T* uR = &fp[((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4];
+    T ub[4];
+    const T* uR = ub;
+    if (R >= 0)
+      uR = &fp[((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4];
+    else
+      boundary_state(m, m.bidx[f], uL, m.fn[2 * f], m.fn[2 * f + 1], ub);
     T F[4];
     hll_flux(uL, uR, m.fn[2 * f], m.fn[2 * f + 1], m.prm.gamma, F);
     for (int c = 0; c < 4; ++c) phi[c] += m.gq_w[k] * F[c];
@@ -1087,7 +1126,9 @@ void oracle_default_params(oracle_params* p) {
   p->dk_prime = 1e4;
 }
 
-// Geometry and faces (Sec. 2.1).  period may be NULL (no periodic wrap).
+// Geometry and faces (Sec. 2.1).  period: per axis, 0 = open axis; NULL =
+// both open.  Edges with one cell are boundary faces, allowed when an axis
+// is open.
 void* oracle_mesh_create(int nv, const double* xy, int nc, const int* tri, const double* period) {
   if (nv <= 0 || nc <= 0 || !xy || !tri) { fail("empty mesh"); return nullptr; }
   Mesh* m = new Mesh();
@@ -1096,10 +1137,10 @@ void* oracle_mesh_create(int nv, const double* xy, int nc, const int* tri, const
   m->xy.assign(xy, xy + 2 * (size_t)nv);
   m->tri.assign(tri, tri + 3 * (size_t)nc);
   if (period) {
-    m->periodic = true;
-    m->P[0] = period[0];
-    m->P[1] = period[1];
+    m->P[0] = period[0] > 0.0 ? period[0] : 0.0;
+    m->P[1] = period[1] > 0.0 ? period[1] : 0.0;
   }
+  m->periodic = m->P[0] > 0.0 && m->P[1] > 0.0;
   m->X.assign((size_t)nc * 6, 0.0);
   m->area.assign(nc, 0.0);
   m->cen.assign(2 * (size_t)nc, 0.0);
@@ -1152,9 +1193,27 @@ void* oracle_mesh_create(int nv, const double* xy, int nc, const int* tri, const
     int ci = he[t].second / 3, ce = he[t].second % 3;
     auto it = std::lower_bound(he.begin(), he.end(), std::make_pair(std::make_pair(b, a), -1));
     if (it == he.end() || it->first != std::make_pair(b, a)) {
-      fail("open edge (boundary edges are not supported)");
-      delete m;
-      return nullptr;
+      if (m->periodic) {
+        fail("open edge on a mesh periodic in both axes");
+        delete m;
+        return nullptr;
+      }
+      // boundary face: the cell's edge, normal pointing out of the domain
+      int f = m->nf++;
+      m->fL.push_back(ci);
+      m->fLe.push_back(ce);
+      m->fR.push_back(-1);
+      m->fRe.push_back(-1);
+      const double* X = &m->X[(size_t)ci * 6];
+      double ex = X[2 * ((ce + 1) % 3)] - X[2 * ce];
+      double ey = X[2 * ((ce + 1) % 3) + 1] - X[2 * ce + 1];
+      double len = std::sqrt(ex * ex + ey * ey);
+      m->flen.push_back(len);
+      m->fn.push_back(ey / len);
+      m->fn.push_back(-ex / len);
+      m->cf[3 * ci + ce] = f;
+      m->bface.push_back(f);
+      continue;
     }
     int cj = it->second / 3, cje = it->second % 3;
     if (ci > cj || (ci == cj && ce > cje)) continue;  // the other half creates it
@@ -1173,7 +1232,36 @@ void* oracle_mesh_create(int nv, const double* xy, int nc, const int* tri, const
     m->cf[3 * ci + ce] = f;
     m->cf[3 * cj + cje] = f;
   }
+  m->bidx.assign(m->nf, -1);
+  for (size_t b = 0; b < m->bface.size(); ++b) m->bidx[m->bface[b]] = (int)b;
+  m->bkind.assign(m->bface.size(), 1);
+  m->bstate.assign(4 * m->bface.size(), 0.0);
   return m;
+}
+
+int oracle_boundary_count(void* h) { return (int)((Mesh*)h)->bface.size(); }
+
+// verts [nb][2] (user vertex ids, counter-clockwise in the cell), cell [nb]
+int oracle_boundary_faces(void* h, int* verts, int* cell) {
+  Mesh* m = (Mesh*)h;
+  for (size_t b = 0; b < m->bface.size(); ++b) {
+    int f = m->bface[b], i = m->fL[f], e = m->fLe[f];
+    verts[2 * b] = m->tri[3 * i + e];
+    verts[2 * b + 1] = m->tri[3 * i + (e + 1) % 3];
+    if (cell) cell[b] = i;
+  }
+  return 0;
+}
+
+// kind [nb] (1 transmissive, 2 reflective, 3 prescribed), state [nb][4]
+int oracle_set_boundary(void* h, const int* kind, const double* state) {
+  Mesh* m = (Mesh*)h;
+  for (size_t b = 0; b < m->bface.size(); ++b) {
+    if (kind[b] < 1 || kind[b] > 3) return fail("boundary kind must be 1, 2 or 3");
+    m->bkind[b] = kind[b];
+    for (int c = 0; c < 4; ++c) m->bstate[4 * b + c] = state ? state[4 * b + c] : 0.0;
+  }
+  return 0;
 }
 
 void oracle_mesh_destroy(void* h) { delete (Mesh*)h; }
@@ -1458,7 +1546,8 @@ int oracle_residual_cells(void* h, const double* U, int n, const int* cells, dou
     need.push_back(i);
     for (int e = 0; e < 3; ++e) {
       int f = m->cf[3 * i + e];
-      need.push_back(m->fL[f] == i && m->fLe[f] == e ? m->fR[f] : m->fL[f]);
+      int other = m->fL[f] == i && m->fLe[f] == e ? m->fR[f] : m->fL[f];
+      if (other >= 0) need.push_back(other);
     }
   }
   std::sort(need.begin(), need.end());
@@ -1483,11 +1572,16 @@ int oracle_residual_cells(void* h, const double* U, int n, const int* cells, dou
     for (int e = 0; e < 3; ++e) {
       int f = m->cf[3 * i + e];
       int L = m->fL[f], R = m->fR[f], eL = m->fLe[f], eR = m->fRe[f];
-      size_t sL = slot(L), sR = slot(R);
+      size_t sL = slot(L), sR = R >= 0 ? slot(R) : 0;
       double phi[4] = {0, 0, 0, 0};
       for (int k = 0; k < nq; ++k) {
         const double* uL = &fpn[(sL * 3 * nq + eL * nq + k) * 4];
-        const double* uR = &fpn[(sR * 3 * nq + eR * nq + (nq - 1 - k)) * 4];
+        double ub[4];
+        const double* uR = ub;
+        if (R >= 0)
+          uR = &fpn[(sR * 3 * nq + eR * nq + (nq - 1 - k)) * 4];
+        else
+          boundary_state(*m, m->bidx[f], uL, m->fn[2 * f], m->fn[2 * f + 1], ub);
         double F[4];
         hll_flux(uL, uR, m->fn[2 * f], m->fn[2 * f + 1], m->prm.gamma, F);
         for (int c = 0; c < 4; ++c) phi[c] += m->gq_w[k] * F[c];
@@ -1567,6 +1661,7 @@ int oracle_jvp(void* h, const double* U, const uint16_t* flags, const double* v,
   if (!ready(*m)) return -1;
   if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
   if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
+  if (!m->bface.empty()) return fail("no adjoint on a mesh with boundary faces");
   const size_t n4 = 4 * (size_t)m->nc;
   const double hh = 1e-30;
   std::vector<cplx> Uc(n4), Rc(n4);
@@ -1583,6 +1678,7 @@ int oracle_vjp(void* h, const double* U, const uint16_t* flags, const double* la
   if (!ready(*m)) return -1;
   if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
   if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
+  if (!m->bface.empty()) return fail("no adjoint on a mesh with boundary faces");
   const int nq = m->nq, nc = m->nc;
   const size_t n4 = 4 * (size_t)nc;
   // forward face points with the frozen selection

@@ -22,7 +22,23 @@ Initial states (conservative variables rho, rho*u, rho*v, E; gamma = 1.4):
     p ~ U[0.03, 1.5], sampled at cell centroids wrapped into [0, 1)^2.
   * ``wave_plus_jump``: the smooth wave with p multiplied by a ratio
     ~ U[2, 10] on the positive side of one random line.
-  * ``kelvin_helmholtz``: the paper's single-mode KHI state (Sec. 5.8).
+  * ``kelvin_helmholtz``: the paper's single-mode KHI state (Sec. 5.7).
+
+Meshes with boundaries (``jittered_box_mesh``): the same construction on
+[x0, x0 + Lx] x [y0, y0 + Ly] with (Nx + 1) x (Ny + 1) vertices and no wrap;
+interior vertices are jittered on both axes, boundary vertices only along
+their side, corners stay put.  Boundary conditions are assigned per side
+from each boundary face's midpoint:
+  * ``double_mach``: the paper's double Mach reflection (Sec. 5.8) on
+    [0, 4] x [0, 1]: a Mach 10 shock at x = 1/6 + y/sqrt(3) (60 degrees to
+    the wall), post-shock (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5) to its
+    left, (1.4, 0, 0, 1) to its right; bottom prescribed post-shock for
+    x < 1/6 and reflective after it, left prescribed post-shock, right
+    transmissive, top prescribed with the exact shock position
+    1/6 + (1 + 20 t)/sqrt(3) at time t.
+  * ``sod_x``: Sod's shock tube along x on [0, 1] x [0, Ly] (left state
+    (1, 0, 1), right state (0.125, 0, 0.1), jump at x = 0.5), transmissive
+    ends and reflective side walls.
 """
 from __future__ import annotations
 
@@ -42,6 +58,7 @@ class MeshData:
     period: tuple = (1.0, 1.0)
     seed: int = 0
     rng: np.random.Generator = field(default=None, repr=False)
+    box: tuple = None       # (x0, y0, lx, ly) of a mesh with open sides
 
     @property
     def n_cell(self) -> int:
@@ -79,13 +96,45 @@ def jittered_periodic_mesh(n: int, seed: int, jitter: float = 0.2) -> MeshData:
                     tri=np.ascontiguousarray(tri.reshape(-1, 3)), seed=seed, rng=rng)
 
 
+def jittered_box_mesh(nx: int, ny: int, seed: int, lx: float = 1.0, ly: float = 1.0,
+                      x0: float = 0.0, y0: float = 0.0, jitter: float = 0.2) -> MeshData:
+    """Nx x Ny x 2 jittered triangulation of a rectangle with open sides."""
+    if nx < 2 or ny < 2:
+        raise ValueError("nx, ny must be >= 2")
+    rng = np.random.default_rng(seed)
+    hx, hy = lx / nx, ly / ny
+    jx = rng.uniform(-jitter * hx, jitter * hx, size=(ny + 1, nx + 1))
+    jy = rng.uniform(-jitter * hy, jitter * hy, size=(ny + 1, nx + 1))
+    jx[:, 0] = jx[:, -1] = 0.0          # left and right sides keep their x
+    jy[0, :] = jy[-1, :] = 0.0          # bottom and top keep their y
+    jj, ii = np.meshgrid(np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    xy = np.stack([x0 + ii * hx + jx, y0 + jj * hy + jy], axis=-1).reshape(-1, 2)
+    cj, ci = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    w = nx + 1
+    v00 = cj * w + ci
+    v10 = cj * w + ci + 1
+    v11 = (cj + 1) * w + ci + 1
+    v01 = (cj + 1) * w + ci
+    tri = np.empty((nx * ny, 2, 3), dtype=np.int32)
+    tri[:, 0, 0] = v00.ravel()
+    tri[:, 0, 1] = v10.ravel()
+    tri[:, 0, 2] = v11.ravel()
+    tri[:, 1, 0] = v00.ravel()
+    tri[:, 1, 1] = v11.ravel()
+    tri[:, 1, 2] = v01.ravel()
+    return MeshData(n=nx, xy=np.ascontiguousarray(xy, dtype=np.float64),
+                    tri=np.ascontiguousarray(tri.reshape(-1, 3)), period=(0.0, 0.0),
+                    seed=seed, rng=rng, box=(x0, y0, lx, ly))
+
+
 def unwrapped_vertices(mesh: MeshData) -> np.ndarray:
     """[n_cell, 3, 2] vertex coordinates with v1, v2 moved to the periodic
-    image nearest to v0."""
+    image nearest to v0 (on the periodic axes)."""
     p = np.asarray(mesh.period, dtype=np.float64)
     v = mesh.xy[mesh.tri]                      # [nc, 3, 2]
     d = v - v[:, :1, :]
-    v = v - np.round(d / p) * p
+    safe = np.where(p > 0, p, 1.0)
+    v = v - np.where(p > 0, np.round(d / safe) * safe, 0.0)
     return v
 
 
@@ -93,7 +142,8 @@ def centroids(mesh: MeshData, wrap: bool = True) -> np.ndarray:
     c = unwrapped_vertices(mesh).mean(axis=1)
     if wrap:
         p = np.asarray(mesh.period)
-        c = c - np.floor(c / p) * p
+        safe = np.where(p > 0, p, 1.0)
+        c = c - np.where(p > 0, np.floor(c / safe) * safe, 0.0)
     return c
 
 
@@ -181,6 +231,68 @@ def kelvin_helmholtz(mesh: MeshData) -> np.ndarray:
     return conservative(rho, u, v, np.full(mesh.n_cell, 2.5))
 
 
+# ---------------------------------------------------------------------------
+# states and boundary conditions on meshes with open sides
+# ---------------------------------------------------------------------------
+BC_TRANSMISSIVE, BC_REFLECTIVE, BC_PRESCRIBED = 1, 2, 3
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+DMR_POST = (8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
+
+
+def face_sides(mesh: MeshData, verts: np.ndarray):
+    """Midpoints [nb, 2] of boundary faces (vertex pairs) and their side:
+    0 left, 1 right, 2 bottom, 3 top."""
+    x0, y0, lx, ly = mesh.box
+    mid = 0.5 * (mesh.xy[verts[:, 0]] + mesh.xy[verts[:, 1]])
+    tol = 1e-9 * max(lx, ly)
+    side = np.full(len(verts), -1, dtype=np.int64)
+    side[np.abs(mid[:, 0] - x0) <= tol] = 0
+    side[np.abs(mid[:, 0] - (x0 + lx)) <= tol] = 1
+    side[np.abs(mid[:, 1] - y0) <= tol] = 2
+    side[np.abs(mid[:, 1] - (y0 + ly)) <= tol] = 3
+    if (side < 0).any():
+        raise ValueError("a boundary face lies on no side of the box")
+    return mid, side
+
+
+def double_mach(mesh: MeshData) -> np.ndarray:
+    """Initial state of the double Mach reflection at cell centroids."""
+    x = centroids(mesh, wrap=False)
+    post = x[:, 0] < 1.0 / 6.0 + x[:, 1] / math.sqrt(3.0)
+    s = np.where(post[:, None], np.array(DMR_POST), np.array(DMR_PRE))
+    return conservative(s[:, 0], s[:, 1], s[:, 2], s[:, 3])
+
+
+def double_mach_boundary(mesh: MeshData, verts: np.ndarray, t: float = 0.0):
+    """(kind [nb], state [nb, 4]) of the double Mach reflection at time t."""
+    mid, side = face_sides(mesh, verts)
+    post = conservative(*DMR_POST)
+    pre = conservative(*DMR_PRE)
+    kind = np.full(len(verts), BC_PRESCRIBED, dtype=np.int32)
+    state = np.tile(post, (len(verts), 1))
+    kind[side == 1] = BC_TRANSMISSIVE
+    wall = (side == 2) & (mid[:, 0] >= 1.0 / 6.0)
+    kind[wall] = BC_REFLECTIVE
+    top = side == 3
+    xs = 1.0 / 6.0 + (1.0 + 20.0 * t) / math.sqrt(3.0)
+    state[top & (mid[:, 0] >= xs)] = pre
+    return kind, np.ascontiguousarray(state)
+
+
+def sod_x(mesh: MeshData) -> np.ndarray:
+    """Sod's shock tube along x: (1, 0, 1) left of x = 0.5, (0.125, 0, 0.1) right."""
+    x = centroids(mesh, wrap=False)
+    left = x[:, 0] < 0.5
+    return conservative(np.where(left, 1.0, 0.125), 0.0, 0.0, np.where(left, 1.0, 0.1))
+
+
+def tube_boundary(mesh: MeshData, verts: np.ndarray):
+    """Transmissive ends (left, right), reflective side walls."""
+    _, side = face_sides(mesh, verts)
+    kind = np.where(side <= 1, BC_TRANSMISSIVE, BC_REFLECTIVE).astype(np.int32)
+    return kind, None
+
+
 def disc_mask(mesh: MeshData, center, radius: float) -> np.ndarray:
     """Cells whose centroid lies within `radius` of `center` (periodic distance)."""
     x = centroids(mesh, wrap=True)
@@ -201,6 +313,9 @@ WORKLOADS = {
     4: dict(name="teno4_adjoint_N256", order=4, n=256, seed=4, ic="random_lines", steps=200),
     # the paper's KHI timing workload at its size (576,738 ~ 577,416 triangles)
     6: dict(name="teno5_khi_N537", order=5, n=537, seed=6, ic="kelvin_helmholtz", steps=100),
+    # the paper's DMR timing workload at its size (369,800 ~ 369,794 triangles)
+    7: dict(name="teno5_dmr_860x215", order=5, n=860, ny=215, lx=4.0, ly=1.0, seed=7,
+            ic="double_mach", steps=100),
 }
 
 
@@ -213,6 +328,10 @@ def make_state(mesh: MeshData, ic: str) -> np.ndarray:
         return wave_plus_jump(mesh)
     if ic == "kelvin_helmholtz":
         return kelvin_helmholtz(mesh)
+    if ic == "double_mach":
+        return double_mach(mesh)
+    if ic == "sod_x":
+        return sod_x(mesh)
     raise ValueError(ic)
 
 
@@ -221,7 +340,12 @@ def make_workload(key: int, n: int | None = None):
     w = dict(WORKLOADS[key])
     if n is not None:
         w["n"] = n
-    mesh = jittered_periodic_mesh(w["n"], w["seed"])
+    if "ny" in w:
+        if n is not None:
+            w["ny"] = max(2, round(n * w["ly"] / w["lx"]))
+        mesh = jittered_box_mesh(w["n"], w["ny"], w["seed"], w["lx"], w["ly"])
+    else:
+        mesh = jittered_periodic_mesh(w["n"], w["seed"])
     u0 = make_state(mesh, w["ic"])
     return w, mesh, u0
 

@@ -50,8 +50,8 @@ MUTANTS = [
     ("left_wave_speed", "T SL = min_re(unL - cL, ut - ct);", "T SL = min_re(unL - cL, ut + ct);"),
     ("rotate_back", "out[1] = F[1] * nx - F[2] * ny;", "out[1] = F[1] * nx + F[2] * ny;"),
     ("face_point_pairing",
-     "const T* uR = &fp[((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4];",
-     "const T* uR = &fp[((size_t)R * 3 * nq + eR * nq + k) * 4];"),
+     "uR = &fp[((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4];",
+     "uR = &fp[((size_t)R * 3 * nq + eR * nq + k) * 4];"),
     ("face_side_sign", "double s = (m.fL[f] == i && m.fLe[f] == e) ? 1.0 : -1.0;",
      "double s = (m.fL[f] == i && m.fLe[f] == e) ? 1.0 : 1.0;"),
     ("residual_sign", "Ri[c] = -acc[c] / m.area[i];", "Ri[c] = acc[c] / m.area[i];"),
@@ -81,6 +81,12 @@ MUTANTS = [
      "wc[k][l] += L[4 * j + v] * coef[j][k][l];"),
     ("char_back_transform", "val += R[4 * c + v] * dw[v][kq];", "val += L[4 * c + v] * dw[v][kq];"),
     ("char_flags_edge", "    flags3[e] = fe;\n", "    flags3[(e + 1) % 3] = fe;\n"),
+    ("wall_normal_reversal", "uR[1] = -mn * nx - mt * ny;", "uR[1] = mn * nx - mt * ny;"),
+    ("wall_tangent_sign", "uR[2] = -mn * ny + mt * nx;", "uR[2] = -mn * ny - mt * nx;"),
+    ("prescribed_state_ignored", "for (int c = 0; c < 4; ++c) uR[c] = T(m.bstate[4 * (size_t)b + c]);",
+     "for (int c = 0; c < 4; ++c) uR[c] = uL[c];"),
+    ("boundary_kind_swap", "  } else if (m.bkind[b] == 2) {", "  } else if (m.bkind[b] == 1) {"),
+    ("stencil_fill_order", "    std::sort(rest.begin(), rest.end());\n", "\n"),
 ]
 
 
