@@ -157,7 +157,7 @@ PAPER_KHI_T_NORM = {"TENO3": 1.32e-6, "TENO4": 1.66e-6, "TENO5": 1.90e-6, "TENO6
 
 
 def khi_timing(torch, teno, inputs, steps=10, warmup=2):
-    """The paper's KHI timing workload (Sec. 5.8, 5.10) at its size: TENO3-6
+    """The paper's KHI timing workload (Sec. 5.7, 5.10) at its size: TENO3-6
     and CWENO5-6 on the 537x537x2 mesh (576,738 cells), per-stage throughput
     and the reconstruction time per RK3 step per element beside the paper's
     t_norm (CPU hardware; context only).  The *_char schemes select in
@@ -194,6 +194,70 @@ def khi_timing(torch, teno, inputs, steps=10, warmup=2):
             "ms_per_step": el * 1e3 / steps,
             "recon_s_per_step_per_element": 3 * rec_ms * 1e-3 / mesh.n_cell,
             "paper_t_norm_cpu": PAPER_KHI_T_NORM.get(name)}
+        del sv, lm, U
+    return out
+
+
+# Tab. runtime analysis (Sec. 5.10), DMR on 369,794 triangles, 56 CPU threads.
+PAPER_DMR_T_NORM = {"TENO3": 1.36e-6, "TENO4": 1.66e-6, "TENO5": 1.96e-6, "TENO6": 2.24e-6,
+                    "CWENO5": 1.98e-6, "CWENO6": 2.20e-6}
+
+
+def dmr_timing(torch, teno, inputs, steps=10, warmup=2):
+    """The paper's DMR timing workload (Sec. 5.8, 5.10) at its size: a Mach 10
+    shock on [0, 4] x [0, 1] with 860 x 215 x 2 = 369,800 cells (paper:
+    369,794), reflective wall, prescribed inflow and moving-shock top,
+    transmissive outflow.  The top boundary follows the exact shock position
+    at the start of every step (its states are computed on the device from
+    the device-resident time)."""
+    w, mesh, U0 = inputs.make_workload(7)
+    out = {"workload": "double_mach_860x215", "n_cell": mesh.n_cell, "steps": steps, "schemes": {}}
+    for name, order, variant in (("TENO3", 3, 0), ("TENO4", 4, 0), ("TENO5", 5, 0), ("TENO6", 6, 0),
+                                 ("CWENO5", 5, 2), ("CWENO6", 6, 2)):
+        lm = teno.Mesh(mesh.xy, mesh.tri, period=mesh.period)
+        verts, _ = lm.boundary_faces()
+        kind, state = inputs.double_mach_boundary(mesh, verts, 0.0)
+        lm.set_boundary(kind, state)
+        lm.setup(order=order, fallback=1, variant=variant)
+        sv = teno.Solver(lm)
+        mid, side = inputs.face_sides(mesh, verts)
+        top = torch.as_tensor((side == 3)[:, None], device="cuda")
+        xmid = torch.as_tensor(mid[:, :1], device="cuda")
+        post = torch.as_tensor(inputs.conservative(*inputs.DMR_POST), device="cuda")
+        pre = torch.as_tensor(inputs.conservative(*inputs.DMR_PRE), device="cuda")
+        base = torch.as_tensor(state, device="cuda")
+        U = torch.as_tensor(U0[lm.perm], device="cuda")
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def step():
+            xs = 1.0 / 6.0 + (1.0 + 20.0 * t) / 3.0 ** 0.5
+            sv.set_boundary_states(torch.where(top, torch.where(xmid < xs, post, pre), base))
+            sv.max_dt(U, 0.4, dt)
+            sv.rk_step(U, dt)
+            t.add_(dt)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        sv.profile_read(reset=True)
+        sv.profile_enable(True, kinds=("reconstruct",))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sv.profile_enable(False)
+        prof = sv.profile_read(reset=True)
+        diag = sv.diagnostics(reset=True)
+        rec_ms = prof.ms["reconstruct"] / max(1, prof.launches["reconstruct"])
+        out["schemes"][name] = {
+            "value": mesh.n_cell * 3 * steps / el, "unit": "cell-updates/s",
+            "ms_per_step": el * 1e3 / steps,
+            "recon_s_per_step_per_element": 3 * rec_ms * 1e-3 / mesh.n_cell,
+            "paper_t_norm_cpu": PAPER_DMR_T_NORM.get(name),
+            "fallback_cells": int(diag["fallbacks"]),
+            "finite": bool(torch.isfinite(U).all().item())}
         del sv, lm, U
     return out
 
@@ -270,6 +334,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-khi", action="store_true", help="skip the KHI TENO3-6 timings")
+    ap.add_argument("--no-dmr", action="store_true", help="skip the DMR TENO3-6 timings")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-launch HIP events (no roofline figures)")
     ap.add_argument("--breakdown-steps", type=int, default=5,
@@ -381,6 +446,8 @@ def main():
         out["batched"] = batch_timing(torch, teno, inputs)
     if not args.no_khi:
         out["khi"] = khi_timing(torch, teno, inputs)
+    if not args.no_dmr:
+        out["dmr"] = dmr_timing(torch, teno, inputs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps,
                                            single=not args.no_cpu_single)

@@ -37,6 +37,18 @@ typedef enum teno_status {
   TENO_ENOMEM = -6     /* host or device allocation failed                     */
 } teno_status;
 
+/* Boundary conditions of boundary faces (meshes with an open axis).  The
+ * paper's shock-tube, explosion and double-Mach-reflection tests (Sec.
+ * 5.4-5.6, 5.8) need walls, inflow and outflow; it does not state how they
+ * are imposed.  Each kind fixes the outer state of the face's Riemann
+ * problem at every Gauss point: */
+typedef enum teno_bc {
+  TENO_BC_TRANSMISSIVE = 1, /* outflow: the inner face state (zero gradient)  */
+  TENO_BC_REFLECTIVE = 2,   /* slip wall: the inner state, normal momentum    */
+                            /* reversed                                       */
+  TENO_BC_PRESCRIBED = 3    /* inflow or far field: a given conservative state */
+} teno_bc;
+
 typedef struct teno_mesh teno_mesh;
 typedef struct teno_solver teno_solver;
 typedef struct teno_batch teno_batch;
@@ -79,6 +91,7 @@ typedef struct teno_info {
   double min_rcond;                  /* min over stencils of min|R_jj|/max|R_jj| */
   int64_t face_state_doubles;        /* one stage's face states in the library  */
                                      /* layout (teno_rk_step, teno_vjp_rk_step) */
+  int64_t n_bface;                   /* boundary faces (0 on a periodic mesh)  */
 } teno_info;
 
 /* Device-side diagnostics, accumulated until reset. */
@@ -97,9 +110,12 @@ void teno_default_params(teno_params* p);
 
 /* Geometry and faces, Sec. 2.1.  xy: host double[n_vert][2]; tri: host
  * int32[n_cell][3] (orientation fixed to counter-clockwise internally by
- * swapping the last two vertices); period: host double[2] of the periodic box,
- * or NULL.  Every edge must be shared by exactly two cells (closed periodic
- * mesh), else TENO_EMESH.  Copies its inputs; *out is owned by the caller. */
+ * swapping the last two vertices); period: host double[2], the period of
+ * each axis or 0 for an open axis; NULL opens both.  On a mesh periodic in
+ * both axes every edge must be shared by exactly two cells, else
+ * TENO_EMESH; with an open axis an edge with one cell is a boundary face
+ * (transmissive until teno_mesh_set_boundary says otherwise).  Copies its
+ * inputs; *out is owned by the caller. */
 int teno_mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
                      const double* period, teno_mesh** out);
 
@@ -118,6 +134,19 @@ int teno_mesh_info(const teno_mesh* m, teno_info* out);
 
 /* perm[internal] = user cell id (host int32[n_cell]). */
 int teno_mesh_permutation(const teno_mesh* m, int32_t* perm);
+
+/* Boundary faces, numbered b = 0 .. n_bface-1 (0 on a doubly periodic
+ * mesh).  verts: host int32[n_bface][2], the user vertex ids of face b in
+ * the counter-clockwise order of its cell; cell: host int32[n_bface] (nullable),
+ * the user id of that cell. */
+int teno_mesh_boundary_count(const teno_mesh* m, int32_t* n_bface);
+int teno_mesh_boundary_faces(const teno_mesh* m, int32_t* verts, int32_t* cell);
+
+/* Boundary condition of every boundary face: kind host int32[n_bface]
+ * (teno_bc), state host double[n_bface][4] conservative (read for
+ * TENO_BC_PRESCRIBED faces; NULL when there are none).  Takes effect for
+ * solvers created afterwards. */
+int teno_mesh_set_boundary(teno_mesh* m, const int32_t* kind, const double* state);
 
 /* Members of stencil k (0..2 directional across local edge k, 3 = central)
  * of USER cell `cell`, as user ids nearest first, target excluded. Returns the
@@ -197,6 +226,12 @@ int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, co
 int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags3,
                      const double* face_states3, const double* dt_dev, const double* lam_out,
                      double* lam_in, void* stream);
+
+/* Replaces the prescribed boundary states (time-dependent inflow, e.g. the
+ * moving shock of the double Mach reflection): state_dev device
+ * double[n_bface][4], copied on `stream`; entries of faces of other kinds are
+ * ignored. */
+int teno_solver_set_boundary_states(teno_solver* s, const double* state_dev, void* stream);
 
 /* Reads (and optionally resets) the device diagnostics; synchronises the
  * stream. */

@@ -48,14 +48,19 @@ int fail(int code, const std::string& msg);
 struct Mesh {
   // ---- geometry, user order ----
   int nv = 0, nc = 0, nf = 0;
-  bool periodic = false;
-  double P[2] = {0.0, 0.0};
+  double P[2] = {0.0, 0.0};           // period per axis, 0 = open axis
+  double lo[2] = {0.0, 0.0}, hi[2] = {1.0, 1.0};  // box of the centroids (open axes)
   std::vector<int32_t> tri;           // [nc][3] counter-clockwise
   std::vector<double> X;              // [nc][3][2] vertices unwrapped about v0
   std::vector<double> area, cen;      // [nc], [nc][2]
   std::vector<int32_t> fL, fR, fLe, fRe;  // face -> L/R cell (user id), local edges
   std::vector<double> fnx, fny, flen;     // unit normal out of L, edge length
   std::vector<int32_t> cface;         // [nc][3] face of each local edge
+  // boundary faces (an edge with one cell, on an open axis): fR = fRe = -1
+  std::vector<int32_t> bface;         // [n_bface] face id, in creation order
+  std::vector<int32_t> bkind;         // [n_bface] TENO_BC_* (default transmissive)
+  std::vector<double> bstate;         // [n_bface][4] prescribed states
+  bool open() const { return !(P[0] > 0.0 && P[1] > 0.0); }
 
   // ---- set-up ----
   bool ready = false;
@@ -77,8 +82,10 @@ struct Mesh {
   std::vector<double> geo;      // [n_pad][10]: (nx, ny, len) x 3 edges, area
   std::vector<int32_t> user_of; // [n_pad] user id (diagnostics)
   // face-ordered flux data: faces sorted by their L cell's internal index
-  std::vector<int32_t> face_cells;  // [nf][4]: L, R (internal), eL | eR << 2, 0
+  std::vector<int32_t> face_cells;  // [nf][4]: L, R (internal; L again on a boundary
+                                    //   face), eL | eR << 2, boundary index or -1
   std::vector<double> face_geo;     // [nf][4]: nx, ny (out of L), |A|, 0
+  std::vector<int32_t> bface_sorted; // [n_bface]: face-ordered index of boundary face b
   std::vector<int32_t> cell_faces;  // [n_pad][4]: sorted face of local edges 0..2;
                                     //   bit e of [3] set when the cell is that face's L
   std::vector<double> vol;          // [n_pad] |V| (1 for padding cells)

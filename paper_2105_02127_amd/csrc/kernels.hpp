@@ -825,15 +825,38 @@ __global__ __launch_bounds__(256) TENO_CHAR_ATTR void k_reconstruct_char(ReconAr
 //               the optional SSP-RK3 stage combine.  A gather: no atomics.
 struct FaceFluxArgs {
   const double* __restrict__ fp;       // [3 nq][n_pad][4]
-  const int4* __restrict__ fcell;      // [n_face]: L, R, eL | eR << 2
+  const int4* __restrict__ fcell;      // [n_face]: L, R, eL | eR << 2, boundary index or -1
   const double2* __restrict__ fgeo;    // [n_face][2]: (nx, ny), (|A|, 0)
   double* __restrict__ phi;            // [n_face][4]
+  const int* __restrict__ bkind;       // [n_bface] TENO_BC_*
+  const double* __restrict__ bstate;   // [n_bface][4] prescribed states
   double gamma;
   int n_face, n_pad;
 };
 
-template <int NQ>
-__device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f) {
+// Outer state of boundary face b at one Gauss point (normal (nx, ny) out of
+// the domain): transmissive copies the inner state, reflective reverses its
+// normal momentum, prescribed takes the given state.
+__device__ __forceinline__ void boundary_state(const FaceFluxArgs& a, int b, const double uL[4],
+                                               double nx, double ny, double uR[4]) {
+  const int kind = a.bkind[b];
+  if (kind == TENO_BC_PRESCRIBED) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) uR[c] = a.bstate[4 * (size_t)b + c];
+  } else if (kind == TENO_BC_REFLECTIVE) {
+    const double mn = uL[1] * nx + uL[2] * ny;
+    uR[0] = uL[0];
+    uR[1] = uL[1] - 2.0 * mn * nx;
+    uR[2] = uL[2] - 2.0 * mn * ny;
+    uR[3] = uL[3];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) uR[c] = uL[c];
+  }
+}
+
+template <int NQ, bool BND = false>
+__device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f, int b = -1) {
   const int4 fc = a.fcell[f];
   const double2 nrm = a.fgeo[2 * (size_t)f], len = a.fgeo[2 * (size_t)f + 1];
   const int eL = fc.z & 3, eR = (fc.z >> 2) & 3;
@@ -842,11 +865,19 @@ __device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f) {
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const size_t oL = ((size_t)(eL * NQ + k) * a.n_pad + fc.x) * 2;
-    const size_t oR = ((size_t)(eR * NQ + NQ - 1 - k) * a.n_pad + fc.y) * 2;
     const double2 l0 = fp2[oL], l1 = fp2[oL + 1];
-    const double2 r0 = fp2[oR], r1 = fp2[oR + 1];
     const double uL[4] = {l0.x, l0.y, l1.x, l1.y};
-    const double uR[4] = {r0.x, r0.y, r1.x, r1.y};
+    double uR[4];
+    if constexpr (BND) {
+      boundary_state(a, b, uL, nrm.x, nrm.y, uR);
+    } else {
+      const size_t oR = ((size_t)(eR * NQ + NQ - 1 - k) * a.n_pad + fc.y) * 2;
+      const double2 r0 = fp2[oR], r1 = fp2[oR + 1];
+      uR[0] = r0.x;
+      uR[1] = r0.y;
+      uR[2] = r1.x;
+      uR[3] = r1.y;
+    }
     double F[4];
     hll<double>(uL, uR, nrm.x, nrm.y, a.gamma, F);
 #pragma unroll
@@ -857,10 +888,21 @@ __device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f) {
   out[1] = make_double2(phi[2] * len.x, phi[3] * len.x);
 }
 
+// Every face, boundary faces included as if their outer side were the cell
+// itself; k_boundary_flux then rewrites the boundary faces.
 template <int NQ>
 __global__ __launch_bounds__(256) void k_face_flux(FaceFluxArgs a) {
   const int f = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (f < a.n_face) face_flux<NQ>(a, f);
+}
+
+// Boundary faces only (after k_face_flux, same stream): bf[b] is the face
+// index of boundary face b, whose outer state comes from its condition.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_boundary_flux(FaceFluxArgs a, const int* __restrict__ bf,
+                                                       int n_bface) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < n_bface) face_flux<NQ, true>(a, bf[b], b);
 }
 
 struct CellUpdateArgs {

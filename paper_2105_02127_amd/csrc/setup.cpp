@@ -78,13 +78,17 @@ static void parallel_for(int n, int threads, F&& f) {
 // ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
+// Minimum-image difference on the periodic axes (kx, ky: periods removed).
 static inline void wrap_delta(const Mesh& m, double& dx, double& dy, double& kx, double& ky) {
   kx = ky = 0.0;
-  if (!m.periodic) return;
-  kx = std::nearbyint(dx / m.P[0]);
-  ky = std::nearbyint(dy / m.P[1]);
-  dx -= m.P[0] * kx;
-  dy -= m.P[1] * ky;
+  if (m.P[0] > 0.0) {
+    kx = std::nearbyint(dx / m.P[0]);
+    dx -= m.P[0] * kx;
+  }
+  if (m.P[1] > 0.0) {
+    ky = std::nearbyint(dy / m.P[1]);
+    dy -= m.P[1] * ky;
+  }
 }
 
 int mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
@@ -92,11 +96,11 @@ int mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t*
   if (n_vert <= 0 || n_cell <= 0 || !xy || !tri) return fail(TENO_EARG, "empty mesh");
   m.nv = n_vert;
   m.nc = n_cell;
-  m.periodic = period != nullptr;
   if (period) {
     m.P[0] = period[0];
     m.P[1] = period[1];
-    if (!(m.P[0] > 0.0 && m.P[1] > 0.0)) return fail(TENO_EARG, "period must be positive");
+    if (!(m.P[0] >= 0.0 && m.P[1] >= 0.0))
+      return fail(TENO_EARG, "period must be positive, or 0 for an open axis");
   }
   m.tri.assign(tri, tri + 3 * (size_t)n_cell);
   m.X.resize(6 * (size_t)n_cell);
@@ -132,6 +136,19 @@ int mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t*
     m.cen[2 * (size_t)i] = (px[0] + px[1] + px[2]) / 3.0;
     m.cen[2 * (size_t)i + 1] = (py[0] + py[1] + py[2]) / 3.0;
   }
+  for (int a = 0; a < 2; ++a) {
+    if (m.P[a] > 0.0) {
+      m.lo[a] = 0.0;
+      m.hi[a] = m.P[a];
+      continue;
+    }
+    m.lo[a] = m.hi[a] = m.cen[a];
+    for (int i = 0; i < n_cell; ++i) {
+      m.lo[a] = std::min(m.lo[a], m.cen[2 * (size_t)i + a]);
+      m.hi[a] = std::max(m.hi[a], m.cen[2 * (size_t)i + a]);
+    }
+    if (!(m.hi[a] > m.lo[a])) m.hi[a] = m.lo[a] + 1.0;
+  }
   // Faces from directed edges: key (a, b) -> half-edge 3*cell+e.  An
   // undirected edge is one face; L is the cell with the lower user id.
   const size_t nh = 3 * (size_t)n_cell;
@@ -153,9 +170,28 @@ int mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t*
     uint64_t twin = (k << 32) | (k >> 32);
     auto it = std::lower_bound(order.begin(), order.end(), twin,
                                [&](int32_t x, uint64_t v) { return key[x] < v; });
-    if (it == order.end() || key[*it] != twin) return fail(TENO_EMESH, "open edge (boundaries unsupported)");
+    const int ci = he / 3, ce = he % 3;
+    if (it == order.end() || key[*it] != twin) {
+      // an edge with one cell: a boundary face, allowed on meshes with an open axis
+      if (!m.open()) return fail(TENO_EMESH, "open edge on a mesh periodic in both axes");
+      int f = m.nf++;
+      m.fL.push_back(ci);
+      m.fLe.push_back(ce);
+      m.fR.push_back(-1);
+      m.fRe.push_back(-1);
+      const double* X = &m.X[6 * (size_t)ci];
+      double ex = X[2 * ((ce + 1) % 3)] - X[2 * ce];
+      double ey = X[2 * ((ce + 1) % 3) + 1] - X[2 * ce + 1];
+      double len = std::sqrt(ex * ex + ey * ey);
+      m.flen.push_back(len);
+      m.fnx.push_back(ey / len);
+      m.fny.push_back(-ex / len);
+      m.cface[3 * (size_t)ci + ce] = f;
+      m.bface.push_back(f);
+      continue;
+    }
     int32_t ho = *it;
-    int ci = he / 3, ce = he % 3, co = ho / 3, coe = ho % 3;
+    int co = ho / 3, coe = ho % 3;
     if (co < ci || (co == ci && coe < ce)) continue;  // created from the other side
     int f = m.nf++;
     m.fL.push_back(ci);
@@ -172,12 +208,15 @@ int mesh_create(int32_t n_vert, const double* xy, int32_t n_cell, const int32_t*
     m.cface[3 * (size_t)ci + ce] = f;
     m.cface[3 * (size_t)co + coe] = f;
   }
+  m.bkind.assign(m.bface.size(), TENO_BC_TRANSMISSIVE);
+  m.bstate.assign(4 * m.bface.size(), 0.0);
   return TENO_OK;
 }
 
 // ---------------------------------------------------------------------------
-// neighbour search: uniform bins over the periodic box, search radius grown
-// until the wanted count is found strictly inside the covered disc
+// neighbour search: uniform bins over the box (periodic axes wrap), search
+// radius grown until the wanted count is found strictly inside the covered
+// disc or every bin is covered
 // ---------------------------------------------------------------------------
 struct Bins {
   int n = 1;
@@ -185,17 +224,21 @@ struct Bins {
   std::vector<int32_t> start, cells;
 };
 
+// Bin coordinate of a centroid along axis a (periodic axes wrap).
+static inline double bin_coord(const Mesh& m, int a, double x) {
+  if (m.P[a] > 0.0) return x - m.P[a] * std::floor(x / m.P[a]);
+  return x - m.lo[a];
+}
+
 static void bins_build(const Mesh& m, Bins& b) {
-  double lx = m.periodic ? m.P[0] : 1.0, ly = m.periodic ? m.P[1] : 1.0;
+  double lx = m.hi[0] - m.lo[0], ly = m.hi[1] - m.lo[1];
   b.n = std::max(1, (int)std::floor(std::sqrt(m.nc * 0.5)));
   b.wx = lx / b.n;
   b.wy = ly / b.n;
   std::vector<int32_t> id(m.nc);
   b.start.assign((size_t)b.n * b.n + 1, 0);
   for (int i = 0; i < m.nc; ++i) {
-    double x = m.cen[2 * (size_t)i], y = m.cen[2 * (size_t)i + 1];
-    x -= lx * std::floor(x / lx);
-    y -= ly * std::floor(y / ly);
+    double x = bin_coord(m, 0, m.cen[2 * (size_t)i]), y = bin_coord(m, 1, m.cen[2 * (size_t)i + 1]);
     int bx = std::min(b.n - 1, std::max(0, (int)(x / b.wx)));
     int by = std::min(b.n - 1, std::max(0, (int)(y / b.wy)));
     id[i] = by * b.n + bx;
@@ -227,8 +270,8 @@ static inline bool cone_ok(const Mesh& m, int i, int k, double dx, double dy) {
   return (dx * by - dy * bx) >= 0.0 && (ax * dy - ay * dx) >= 0.0;
 }
 
-static bool find_stencil(const Mesh& m, const Bins& b, int i, int k, int want,
-                         std::vector<Hit>& scratch, int32_t* out) {
+// Cells j != i passing the cone test of stencil k, by distance.
+static void search(const Mesh& m, const Bins& b, int i, int k, int want, std::vector<Hit>& scratch) {
   double cx = m.cen[2 * (size_t)i], cy = m.cen[2 * (size_t)i + 1];
   auto consider = [&](int j) {
     if (j == i) return;
@@ -238,23 +281,37 @@ static bool find_stencil(const Mesh& m, const Bins& b, int i, int k, int want,
     scratch.push_back({dx * dx + dy * dy, j});
   };
   scratch.clear();
-  bool full = !m.periodic || b.n < 7;
+  bool full = b.n < 7;
   if (!full) {
-    double lx = m.P[0], ly = m.P[1];
-    double x = cx - lx * std::floor(cx / lx), y = cy - ly * std::floor(cy / ly);
-    int bx0 = std::min(b.n - 1, std::max(0, (int)(x / b.wx)));
-    int by0 = std::min(b.n - 1, std::max(0, (int)(y / b.wy)));
-    double w = std::min(b.wx, b.wy);
+    const int bx0 = std::min(b.n - 1, std::max(0, (int)(bin_coord(m, 0, cx) / b.wx)));
+    const int by0 = std::min(b.n - 1, std::max(0, (int)(bin_coord(m, 1, cy) / b.wy)));
+    const double w = std::min(b.wx, b.wy);
     int rad = 1;
     for (;;) {
-      if (2 * rad + 1 > b.n) {
+      // bin range per axis: a periodic axis wraps (whole axis once the block
+      // would overlap itself), an open axis is clipped
+      int lo[2], hi[2];
+      bool whole[2];
+      const int c0[2] = {bx0, by0};
+      for (int a = 0; a < 2; ++a) {
+        if (m.P[a] > 0.0) {
+          whole[a] = 2 * rad + 1 > b.n;
+          lo[a] = whole[a] ? 0 : c0[a] - rad;
+          hi[a] = whole[a] ? b.n - 1 : c0[a] + rad;
+        } else {
+          lo[a] = std::max(0, c0[a] - rad);
+          hi[a] = std::min(b.n - 1, c0[a] + rad);
+          whole[a] = lo[a] == 0 && hi[a] == b.n - 1;
+        }
+      }
+      if (whole[0] && whole[1]) {
         full = true;
         break;
       }
       scratch.clear();
-      for (int oy = -rad; oy <= rad; ++oy)
-        for (int ox = -rad; ox <= rad; ++ox) {
-          int bx = (bx0 + ox + b.n) % b.n, by = (by0 + oy + b.n) % b.n;
+      for (int oy = lo[1]; oy <= hi[1]; ++oy)
+        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+          int bx = (ox + b.n) % b.n, by = (oy + b.n) % b.n;
           int bin = by * b.n + bx;
           for (int t = b.start[bin]; t < b.start[bin + 1]; ++t) consider(b.cells[t]);
         }
@@ -271,10 +328,26 @@ static bool find_stencil(const Mesh& m, const Bins& b, int i, int k, int want,
     scratch.clear();
     for (int j = 0; j < m.nc; ++j) consider(j);
   }
-  if ((int)scratch.size() < want) return false;
-  std::partial_sort(scratch.begin(), scratch.begin() + want, scratch.end(), hit_less);
-  for (int s = 0; s < want; ++s) out[s] = scratch[s].id;
-  return true;
+}
+
+// Stencil k of cell i: the `want` nearest cells in the closed cone (k < 3)
+// or overall (k = 3).  Near a boundary a cone may hold fewer cells; the
+// stencil is then completed with the nearest cells outside the cone.
+static bool find_stencil(const Mesh& m, const Bins& b, int i, int k, int want,
+                         std::vector<Hit>& scratch, int32_t* out) {
+  search(m, b, i, k, want, scratch);
+  int have = std::min<int>(want, (int)scratch.size());
+  std::partial_sort(scratch.begin(), scratch.begin() + have, scratch.end(), hit_less);
+  for (int s = 0; s < have; ++s) out[s] = scratch[s].id;
+  if (have == want) return true;
+  if (k == 3 || !m.open()) return false;
+  search(m, b, i, 3, want + have, scratch);
+  std::sort(scratch.begin(), scratch.end(), hit_less);
+  for (const Hit& h : scratch) {
+    if (have == want) break;
+    if (std::find(out, out + have, h.id) == out + have) out[have++] = h.id;
+  }
+  return have == want;
 }
 
 // ---------------------------------------------------------------------------
@@ -438,7 +511,6 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   if (!(p.ct >= 0.0 && p.ct <= 1.0 / 3.0)) return fail(TENO_EARG, "C_T must lie in [0, 1/3]");
   if (p.power < 1 || p.power > 16) return fail(TENO_EARG, "power must be 1..16");
   if (p.n_quad != 0 && (p.n_quad < 2 || p.n_quad > 3)) return fail(TENO_EARG, "n_quad must be 0, 2 or 3");
-  if (!m.periodic) return fail(TENO_EMESH, "only periodic meshes are supported");
   m.prm = p;
   m.d = dims_for(p.order, p.n_quad);
   const Dims& d = m.d;
@@ -454,9 +526,10 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   if (p.reorder) {
     std::vector<uint32_t> code(nc);
     for (int i = 0; i < nc; ++i) {
-      double x = m.cen[2 * (size_t)i] / m.P[0], y = m.cen[2 * (size_t)i + 1] / m.P[1];
-      x -= std::floor(x);
-      y -= std::floor(y);
+      double x = bin_coord(m, 0, m.cen[2 * (size_t)i]) / (m.hi[0] - m.lo[0]);
+      double y = bin_coord(m, 1, m.cen[2 * (size_t)i + 1]) / (m.hi[1] - m.lo[1]);
+      x = std::min(std::max(x, 0.0), 1.0);
+      y = std::min(std::max(y, 0.0), 1.0);
       uint32_t qx = std::min<uint32_t>(65535u, (uint32_t)(x * 65536.0));
       uint32_t qy = std::min<uint32_t>(65535u, (uint32_t)(y * 65536.0));
       code[i] = spread16(qx) | (spread16(qy) << 1);
@@ -511,7 +584,8 @@ int mesh_setup(Mesh& m, const teno_params& p) {
         double dx = m.cen[2 * (size_t)mem[s]] - m.cen[2 * (size_t)i];
         double dy = m.cen[2 * (size_t)mem[s] + 1] - m.cen[2 * (size_t)i + 1], kx, ky;
         wrap_delta(m, dx, dy, kx, ky);
-        if (std::fabs(dx) > 0.4 * m.P[0] || std::fabs(dy) > 0.4 * m.P[1]) {
+        if ((m.P[0] > 0.0 && std::fabs(dx) > 0.4 * m.P[0]) ||
+            (m.P[1] > 0.0 && std::fabs(dy) > 0.4 * m.P[1])) {
           report(TENO_ESTENCIL, "mesh too small for the stencil at cell " + std::to_string(i));
           return;
         }
@@ -554,6 +628,10 @@ int mesh_setup(Mesh& m, const teno_params& p) {
       bool isL = (m.fL[f] == i && m.fLe[f] == e);
       int other = isL ? m.fR[f] : m.fL[f];
       int oe = isL ? m.fRe[f] : m.fLe[f];
+      if (other < 0) {  // boundary face: the cell itself, as its L side
+        other = i;
+        oe = 0;
+      }
       m.nbinfo[(size_t)t * 4 + e] = m.inv[other];
       bits |= (oe & 3) << (2 * e);
       if (isL) bits |= 1 << (6 + e);
@@ -575,16 +653,24 @@ int mesh_setup(Mesh& m, const teno_params& p) {
     });
     m.face_cells.assign((size_t)m.nf * 4, 0);
     m.face_geo.assign((size_t)m.nf * 4, 0.0);
+    std::vector<int32_t> bidx(m.nf, -1);
+    for (size_t b = 0; b < m.bface.size(); ++b) bidx[m.bface[b]] = (int32_t)b;
     for (int k = 0; k < m.nf; ++k) {
       const int f = order[k];
       rank[f] = k;
+      // a boundary face names its own cell on both sides (the kernel loads
+      // unconditionally and replaces the outer state) and its index in .w
+      const bool bnd = m.fR[f] < 0;
       m.face_cells[(size_t)k * 4 + 0] = m.inv[m.fL[f]];
-      m.face_cells[(size_t)k * 4 + 1] = m.inv[m.fR[f]];
-      m.face_cells[(size_t)k * 4 + 2] = (m.fLe[f] & 3) | ((m.fRe[f] & 3) << 2);
+      m.face_cells[(size_t)k * 4 + 1] = m.inv[bnd ? m.fL[f] : m.fR[f]];
+      m.face_cells[(size_t)k * 4 + 2] = (m.fLe[f] & 3) | (((bnd ? m.fLe[f] : m.fRe[f]) & 3) << 2);
+      m.face_cells[(size_t)k * 4 + 3] = bnd ? bidx[f] : -1;
       m.face_geo[(size_t)k * 4 + 0] = m.fnx[f];
       m.face_geo[(size_t)k * 4 + 1] = m.fny[f];
       m.face_geo[(size_t)k * 4 + 2] = m.flen[f];
     }
+    m.bface_sorted.resize(m.bface.size());
+    for (size_t b = 0; b < m.bface.size(); ++b) m.bface_sorted[b] = rank[m.bface[b]];
     m.cell_faces.assign((size_t)m.n_pad * 4, 0);
     m.vol.assign(m.n_pad, 1.0);
     for (int t = 0; t < nc; ++t) {

@@ -81,6 +81,10 @@ struct teno_solver {
   double* vol = nullptr;
   double* phi = nullptr;    // face fluxes of the last stage
   int n_face = 0;
+  int n_bface = 0;
+  int* bkind = nullptr;     // boundary conditions (meshes with an open axis)
+  double* bstate = nullptr;
+  int* bface = nullptr;     // face-ordered index of each boundary face
   int32_t* user_of = nullptr;
   int32_t* rev_ptr = nullptr;
   int32_t* rev_ent = nullptr;
@@ -221,6 +225,8 @@ int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
   f.fcell = s->fcell;
   f.fgeo = s->fgeo;
   f.phi = s->phi;
+  f.bkind = s->bkind;
+  f.bstate = s->bstate;
   f.gamma = s->prm.gamma;
   f.n_face = s->n_face;
   f.n_pad = s->n_pad;
@@ -242,6 +248,9 @@ int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
   auto go = [&](auto NQ) {
     rc = timed(s, 1, st, [&]() {
       hipLaunchKernelGGL((k_face_flux<decltype(NQ)::value>), dim3(fblocks), dim3(256), 0, st, f);
+      if (s->n_bface > 0)
+        hipLaunchKernelGGL((k_boundary_flux<decltype(NQ)::value>), dim3((s->n_bface + 255) / 256),
+                           dim3(256), 0, st, f, (const int*)s->bface, s->n_bface);
       if (rk)
         hipLaunchKernelGGL((k_cell_update<true>), dim3(cblocks), dim3(256), 0, st, c);
       else
@@ -321,6 +330,14 @@ int check_solver(teno_solver* s) {
   return TENO_OK;
 }
 
+// The adjoint and batches cover periodic meshes only (no boundary-condition
+// Jacobians, no per-face boundary data in the batch descriptors).
+int periodic_only(const teno_solver* s, const char* what) {
+  if (s->n_bface > 0)
+    return fail(TENO_EARG, std::string(what) + " needs a periodic mesh (this one has boundary faces)");
+  return TENO_OK;
+}
+
 // CWENO (variant 2) has no selection to freeze and hence no adjoint; the
 // frozen and adjoint paths work in conservative variables only.
 int needs_selection(const teno_solver* s, const char* what) {
@@ -395,6 +412,43 @@ int teno_mesh_info(const teno_mesh* m, teno_info* out) {
     out->min_rcond = x.min_rcond;
     out->face_state_doubles = (int64_t)3 * x.d.nq * x.n_pad * 4;
   }
+  out->n_bface = (int64_t)x.bface.size();
+  return TENO_OK;
+}
+
+int teno_mesh_boundary_count(const teno_mesh* m, int32_t* n_bface) {
+  if (!m || !n_bface) return fail(TENO_EARG, "null argument");
+  *n_bface = (int32_t)m->m.bface.size();
+  return TENO_OK;
+}
+
+int teno_mesh_boundary_faces(const teno_mesh* m, int32_t* verts, int32_t* cell) {
+  if (!m || !verts) return fail(TENO_EARG, "null argument");
+  const Mesh& x = m->m;
+  for (size_t b = 0; b < x.bface.size(); ++b) {
+    const int f = x.bface[b], i = x.fL[f], e = x.fLe[f];
+    verts[2 * b] = x.tri[3 * (size_t)i + e];
+    verts[2 * b + 1] = x.tri[3 * (size_t)i + (e + 1) % 3];
+    if (cell) cell[b] = i;
+  }
+  return TENO_OK;
+}
+
+int teno_mesh_set_boundary(teno_mesh* m, const int32_t* kind, const double* state) {
+  if (!m) return fail(TENO_EARG, "null argument");
+  Mesh& x = m->m;
+  const size_t nb = x.bface.size();
+  if (nb == 0) return TENO_OK;
+  if (!kind) return fail(TENO_EARG, "null argument");
+  for (size_t b = 0; b < nb; ++b) {
+    if (kind[b] < TENO_BC_TRANSMISSIVE || kind[b] > TENO_BC_PRESCRIBED)
+      return fail(TENO_EARG, "boundary kind must be 1, 2 or 3 (face " + std::to_string(b) + ")");
+    if (kind[b] == TENO_BC_PRESCRIBED && !state)
+      return fail(TENO_EARG, "prescribed boundary faces need states");
+  }
+  x.bkind.assign(kind, kind + nb);
+  x.bstate.assign(4 * nb, 0.0);
+  if (state) std::copy(state, state + 4 * nb, x.bstate.begin());
   return TENO_OK;
 }
 
@@ -466,6 +520,10 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
   A(s->M, m.M.size() / 2);
   A(s->nbinfo, np);
   s->n_face = m.nf;
+  s->n_bface = (int)m.bface.size();
+  A(s->bkind, std::max<size_t>(1, m.bkind.size()));
+  A(s->bface, std::max<size_t>(1, m.bface_sorted.size()));
+  A(s->bstate, std::max<size_t>(4, m.bstate.size()));
   A(s->fcell, (size_t)m.nf);
   A(s->fgeo, (size_t)m.nf * 2);
   A(s->cfaces, np);
@@ -498,6 +556,9 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
              {s->tmem, m.tmem.data(), m.tmem.size() * sizeof(int32_t)},
              {s->M, m.M.data(), m.M.size() * sizeof(double)},
              {s->nbinfo, m.nbinfo.data(), m.nbinfo.size() * sizeof(int32_t)},
+             {s->bkind, m.bkind.data(), m.bkind.size() * sizeof(int32_t)},
+             {s->bface, m.bface_sorted.data(), m.bface_sorted.size() * sizeof(int32_t)},
+             {s->bstate, m.bstate.data(), m.bstate.size() * sizeof(double)},
              {s->fcell, m.face_cells.data(), m.face_cells.size() * sizeof(int32_t)},
              {s->fgeo, m.face_geo.data(), m.face_geo.size() * sizeof(double)},
              {s->cfaces, m.cell_faces.data(), m.cell_faces.size() * sizeof(int32_t)},
@@ -638,6 +699,7 @@ int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, co
                       double* U_bar, void* stream) {
   if (int rc = check_solver(s)) return rc;
   if (int rc = needs_selection(s, "vjp_residual")) return rc;
+  if (int rc = periodic_only(s, "vjp_residual")) return rc;
   if (!U || !flags || !lam || !U_bar) return fail(TENO_EARG, "null argument");
   if (U_bar == lam) return fail(TENO_EARG, "U_bar must not alias lam");
   DeviceScope ds(s->device);
@@ -649,6 +711,7 @@ int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags
                      double* lam_in, void* stream) {
   if (int rc = check_solver(s)) return rc;
   if (int rc = needs_selection(s, "vjp_rk_step")) return rc;
+  if (int rc = periodic_only(s, "vjp_rk_step")) return rc;
   if (!stages || !flags3 || !dt_dev || !lam_out || !lam_in) return fail(TENO_EARG, "null argument");
   DeviceScope ds(s->device);
   hipStream_t st = (hipStream_t)stream;
@@ -669,6 +732,17 @@ int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags
   rc = launch_vjp(s, U0, flags3, s->T1, dt_dev, 1.0, s->T1, 1.0, s->T0, st, fs(0));
   if (rc) return rc;
   return lincomb(s, lam_in, 1.0 / 3.0, lam_out, 0.75, s->T2, 1.0, s->T0, st);
+}
+
+int teno_solver_set_boundary_states(teno_solver* s, const double* state_dev, void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (s->n_bface == 0) return TENO_OK;
+  if (!state_dev) return fail(TENO_EARG, "null argument");
+  DeviceScope ds(s->device);
+  hipError_t e = hipMemcpyAsync(s->bstate, state_dev, (size_t)s->n_bface * 4 * sizeof(double),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  return TENO_OK;
 }
 
 int teno_diagnostics(teno_solver* s, teno_diag* out, int32_t reset, void* stream) {
@@ -972,6 +1046,8 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
     f.fcell = s->fcell;
     f.fgeo = s->fgeo;
     f.phi = s->phi;
+    f.bkind = s->bkind;
+    f.bstate = s->bstate;
     f.gamma = s->prm.gamma;
     f.n_face = s->n_face;
     f.n_pad = s->n_pad;
@@ -1040,6 +1116,7 @@ int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out) 
     for (int k = 0; k < m; ++k)
       if (solvers[k] == solvers[m]) return fail(TENO_EARG, "a solver appears twice in the batch");
     if (solvers[m]->prm.variant == 2) return fail(TENO_EARG, "CWENO meshes cannot be batched");
+    if (int rc = periodic_only(solvers[m], "a batch")) return rc;
     if (solvers[m]->prm.characteristic)
       return fail(TENO_EARG, "meshes in characteristic variables cannot be batched");
   }

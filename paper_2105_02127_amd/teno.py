@@ -31,7 +31,8 @@ class Info(C.Structure):
                 ("n_quad", C.c_int32), ("n_coef_large", C.c_int32), ("rows_large", C.c_int32),
                 ("n_coef_small", C.c_int32), ("rows_small", C.c_int32),
                 ("matrix_doubles_per_cell", C.c_int64), ("device_bytes", C.c_int64),
-                ("min_rcond", C.c_double), ("face_state_doubles", C.c_int64)]
+                ("min_rcond", C.c_double), ("face_state_doubles", C.c_int64),
+                ("n_bface", C.c_int64)]
 
 
 class BatchTuning(C.Structure):
@@ -53,6 +54,9 @@ SIGNATURES = {
     "teno_mesh_setup": (C.c_int, [_vp, C.POINTER(Params)]),
     "teno_mesh_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "teno_mesh_permutation": (C.c_int, [_vp, _ip]),
+    "teno_mesh_boundary_count": (C.c_int, [_vp, _ip]),
+    "teno_mesh_boundary_faces": (C.c_int, [_vp, _ip, _ip]),
+    "teno_mesh_set_boundary": (C.c_int, [_vp, _ip, _dp]),
     "teno_mesh_stencil": (C.c_int, [_vp, _i32, _i32, _ip]),
     "teno_mesh_lsq_operator": (C.c_int, [_vp, _i32, _i32, _dp]),
     "teno_mesh_destroy": (None, [_vp]),
@@ -67,6 +71,7 @@ SIGNATURES = {
     "teno_vjp_residual": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "teno_vjp_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "teno_diagnostics": (C.c_int, [_vp, C.POINTER(Diag), _i32, _vp]),
+    "teno_solver_set_boundary_states": (C.c_int, [_vp, _vp, _vp]),
     "teno_profile_enable": (C.c_int, [_vp, _i32]),
     "teno_profile_read": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64), _i32]),
     "teno_batch_create": (C.c_int, [C.POINTER(_vp), _i32, C.POINTER(_vp)]),
@@ -153,8 +158,13 @@ def _ptr(t, shape=None, dtype=None, name="tensor", nullable=False):
     return C.c_void_p(t.data_ptr())
 
 
+# boundary-condition kinds (teno_bc)
+BC_TRANSMISSIVE, BC_REFLECTIVE, BC_PRESCRIBED = 1, 2, 3
+
+
 class Mesh:
-    """Periodic triangle mesh plus (after `setup`) stencils and operators."""
+    """Triangle mesh plus (after `setup`) stencils and operators.  period:
+    the period of each axis, 0 for an open axis (None: both open)."""
 
     def __init__(self, xy, tri, period=(1.0, 1.0)):
         L = load()
@@ -210,6 +220,23 @@ class Mesh:
         out = np.empty(n, dtype=np.int32)
         _check(load().teno_mesh_stencil(self.h, int(cell), int(k), out.ctypes.data_as(_ip)))
         return out
+
+    def boundary_faces(self):
+        """(verts [n_bface, 2], cell [n_bface]) of the boundary faces."""
+        n = C.c_int32()
+        _check(load().teno_mesh_boundary_count(self.h, C.byref(n)))
+        v = np.empty((n.value, 2), dtype=np.int32)
+        c = np.empty(n.value, dtype=np.int32)
+        _check(load().teno_mesh_boundary_faces(self.h, v.ctypes.data_as(_ip), c.ctypes.data_as(_ip)))
+        return v, c
+
+    def set_boundary(self, kind, state=None):
+        """kind: int [n_bface] of BC_*; state: [n_bface, 4] for prescribed faces."""
+        k = np.ascontiguousarray(kind, dtype=np.int32)
+        st = None if state is None else np.ascontiguousarray(state, dtype=np.float64)
+        _check(load().teno_mesh_set_boundary(self.h, k.ctypes.data_as(_ip),
+                                             None if st is None else st.ctypes.data_as(_dp)))
+        return self
 
     def lsq_operator(self, cell: int, k: int) -> np.ndarray:
         i = self.info()
@@ -358,6 +385,13 @@ class Solver:
             self._dt(dt), self._state(lam_out, "lam_out"), self._state(lam_in, "lam_in"),
             _stream(stream)))
         return lam_in
+
+    def set_boundary_states(self, state, stream=None):
+        """Replaces the prescribed boundary states: device float64 [n_bface, 4]."""
+        import torch
+        n = int(self.mesh.info().n_bface)
+        _check(load().teno_solver_set_boundary_states(
+            self.h, _ptr(state, (n, 4), torch.float64, "state"), _stream(stream)))
 
     def diagnostics(self, reset=False, stream=None) -> dict:
         d = Diag()

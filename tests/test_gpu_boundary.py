@@ -1,0 +1,208 @@
+"""GPU parity on meshes with boundaries: transmissive, reflective and
+prescribed faces (the library against the CPU oracle, same seeded inputs).
+Bars as in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+from paper_2105_02127_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def teno():
+    from paper_2105_02127_amd import teno as t
+    t.load()
+    return t
+
+
+def _assert_states(x, y, what):
+    x = np.asarray(x).reshape(-1, 4)
+    y = np.asarray(y).reshape(-1, 4)
+    for v in range(4):
+        err = np.abs(x[:, v] - y[:, v]).max()
+        ref = np.abs(y[:, v]).max()
+        assert err <= REL * ref, f"{what} variable {v}: max err {err:.3e} vs {REL:.0e} * {ref:.3e}"
+
+
+def _nibbles_differ(a, b):
+    d = np.asarray(a, dtype=np.uint16) ^ np.asarray(b, dtype=np.uint16)
+    return int(sum(((d >> (4 * v)) & 0xF != 0).sum() for v in range(4)))
+
+
+def _flux_scale(U, om):
+    """max_i sum_faces |A| |F(U_i).n| / |V_i| over the cells (boundary faces
+    included)."""
+    f = om.faces()
+    area, _, _ = om.geometry()
+    r, mx, my, e = U.T
+    vx, vy = mx / r, my / r
+    p = 0.4 * (e - 0.5 * r * (vx * vx + vy * vy))
+    acc = np.zeros(len(U))
+    for side in ("L", "R"):
+        c = f[side]
+        ok = c >= 0
+        c = c[ok]
+        nrm = f["normal"][ok]
+        un = vx[c] * nrm[:, 0] + vy[c] * nrm[:, 1]
+        Fm = np.abs(np.stack([r[c] * un, mx[c] * un + p[c] * nrm[:, 0], my[c] * un + p[c] * nrm[:, 1],
+                              un * (e[c] + p[c])], 1)).max(1)
+        np.add.at(acc, c, f["length"][ok] * Fm)
+    return float((acc / area).max())
+
+
+def _cell_flux_scale(U, om, cells):
+    """max over `cells` of sum_faces |A| |F(U_i).n| / |V_i| (own state only)."""
+    f = om.faces()
+    area, _, _ = om.geometry()
+    cf = f["cell_face"][cells]
+    r, mx, my, e = U[cells].T
+    vx, vy = mx / r, my / r
+    p = 0.4 * (e - 0.5 * r * (vx * vx + vy * vy))
+    acc = np.zeros(len(cells))
+    for k in range(3):
+        nrm = f["normal"][cf[:, k]]
+        un = vx * nrm[:, 0] + vy * nrm[:, 1]
+        Fm = np.abs(np.stack([r * un, mx * un + p * nrm[:, 0], my * un + p * nrm[:, 1],
+                              un * (e + p)], 1)).max(1)
+        acc += f["length"][cf[:, k]] * Fm
+    return float((acc / area[cells]).max())
+
+
+class Box:
+    """A box mesh with mixed boundary kinds on both sides."""
+
+    def __init__(self, teno, oracle_mod, torch, nx, ny, seed, order, variant=0, characteristic=0,
+                 kinds=(3, 1, 2, 3), ic="random_lines"):
+        print(f"[box] {nx}x{ny} seed={seed} order={order} variant={variant} "
+              f"characteristic={characteristic} kinds={kinds} ic={ic}", flush=True)
+        self.m = inputs.jittered_box_mesh(nx, ny, seed, 1.0 * nx / ny, 1.0)
+        m = self.m
+        self.U = inputs.make_state(m, ic)
+        self.om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+        self.lm = teno.Mesh(m.xy, m.tri, period=m.period)
+        v, c = self.om.boundary_faces()
+        v2, c2 = self.lm.boundary_faces()
+        np.testing.assert_array_equal(v, v2)
+        np.testing.assert_array_equal(c, c2)
+        _, side = inputs.face_sides(m, v)
+        self.kind = np.asarray(kinds, dtype=np.int32)[side]
+        rng = np.random.default_rng(seed)
+        prim = np.stack([rng.uniform(0.5, 1.5, len(v)), rng.uniform(-0.5, 0.5, len(v)),
+                         rng.uniform(-0.5, 0.5, len(v)), rng.uniform(0.5, 1.5, len(v))], 1)
+        self.state = inputs.conservative(*prim.T)
+        self.om.set_boundary(self.kind, self.state)
+        self.lm.set_boundary(self.kind, self.state)
+        kw = dict(order=order, fallback=1, variant=variant, characteristic=characteristic)
+        self.om.setup(oracle_mod.params(**kw))
+        self.lm.setup(**kw)
+        self.sv = teno.Solver(self.lm)
+        self.perm = self.lm.perm
+        self.torch = torch
+        self.Ud = torch.as_tensor(self.U[self.perm], device="cuda")
+
+    def host_user(self, t):
+        a = t.cpu().numpy()
+        out = np.empty_like(a)
+        out[self.perm] = a
+        return out
+
+    def flags_user(self, t):
+        a = t.cpu().numpy().view(np.uint16)
+        out = np.empty_like(a)
+        out[..., self.perm] = a
+        return out
+
+
+@pytest.mark.parametrize("order,variant,characteristic", [(3, 0, 0), (4, 0, 0), (5, 0, 0),
+                                                          (6, 0, 0), (5, 2, 0), (5, 0, 1)])
+def test_box_matches_oracle(teno, oracle_mod, torch_cuda, order, variant, characteristic):
+    torch = torch_cuda
+    b = Box(teno, oracle_mod, torch, 30, 16, 40 + order, order, variant, characteristic)
+    ores = b.om.residual(b.U, want_fp=True)
+    flags = b.sv.empty_flags()
+    fs = b.sv.reconstruct(b.Ud, flags=flags)
+    R = b.sv.residual(b.Ud)
+    torch.cuda.synchronize()
+    fs_user = np.empty((b.m.n_cell, fs.shape[0], 4))
+    fs_user[b.perm] = fs.permute(1, 0, 2).cpu().numpy()
+    _assert_states(fs_user, ores["fp"].reshape(b.m.n_cell, -1, 4), "face states")
+    assert _nibbles_differ(b.flags_user(flags), ores["flags"]) <= ores["diag"]["near_ties"]
+    assert np.abs(b.host_user(R) - ores["R"]).max() <= REL * _flux_scale(b.U, b.om)
+    dto = b.om.dt(b.U, 0.4)
+    dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
+    assert abs(b.sv.max_dt(b.Ud, 0.4).item() - dto) <= 1e-13 * dto
+    ref = b.om.rk_step(b.U, dto)
+    Ud = b.Ud.clone()
+    b.sv.rk_step(Ud, dt)
+    torch.cuda.synchronize()
+    _assert_states(b.host_user(Ud), ref["U"], "U^{n+1}")
+
+
+def test_box_prescribed_states_update_on_device(teno, oracle_mod, torch_cuda):
+    torch = torch_cuda
+    b = Box(teno, oracle_mod, torch, 24, 12, 77, 4)
+    new = b.state[::-1].copy()
+    b.om.set_boundary(b.kind, new)
+    b.sv.set_boundary_states(torch.as_tensor(new, device="cuda"))
+    R = b.sv.residual(b.Ud)
+    torch.cuda.synchronize()
+    ores = b.om.residual(b.U)
+    assert np.abs(b.host_user(R) - ores["R"]).max() <= REL * _flux_scale(b.U, b.om)
+
+
+def test_box_refuses_adjoint_and_batch(teno, oracle_mod, torch_cuda):
+    from paper_2105_02127_amd.batch import Batch
+    b = Box(teno, oracle_mod, torch_cuda, 16, 8, 79, 3)
+    flags = b.sv.empty_flags()
+    b.sv.residual(b.Ud, flags=flags)
+    with pytest.raises(teno.TenoError):
+        b.sv.vjp_residual(b.Ud, flags, b.Ud)
+    with pytest.raises(teno.TenoError):
+        Batch([b.sv])
+
+
+def test_full_size_double_mach_sampled(teno, oracle_mod, torch_cuda):
+    # the paper's DMR workload at its timing size (369,800 cells), TENO5, in
+    # the bench's launch configuration; sampled cells against the oracle
+    torch = torch_cuda
+    w, m, U = inputs.make_workload(7)
+    print(f"[full-size] {w['name']} cells={m.n_cell}", flush=True)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period)
+    verts, _ = lm.boundary_faces()
+    kind, state = inputs.double_mach_boundary(m, verts, 0.0)
+    lm.set_boundary(kind, state)
+    lm.setup(order=w["order"], fallback=1)
+    sv = teno.Solver(lm)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    om.set_boundary(kind, state)
+    om.setup(oracle_mod.params(order=w["order"], fallback=1), all_cells=False)
+    perm = lm.perm
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(m.n_cell)
+    rng = np.random.default_rng(7)
+    _, bcells = lm.boundary_faces()
+    cells = np.unique(np.concatenate([rng.integers(0, m.n_cell, 48), bcells[::97], perm[-3:]]))
+    Ud = torch.as_tensor(U[perm], device="cuda")
+    flags = sv.empty_flags()
+    fs = sv.reconstruct(Ud, flags=flags)
+    R = sv.residual(Ud)
+    torch.cuda.synchronize()
+    fp, ofl, _, odg = om.reconstruct_cells(U, cells)
+    got = fs[:, torch.as_tensor(inv[cells], device="cuda")].permute(1, 0, 2).cpu().numpy()
+    _assert_states(got, fp.reshape(len(cells), -1, 4), "DMR face states")
+    gfl = flags.cpu().numpy().view(np.uint16)[inv[cells]]
+    assert _nibbles_differ(gfl, ofl) <= odg["near_ties"]
+    Ro, _ = om.residual_cells(U, cells)
+    Rg = R.cpu().numpy()[inv[cells]]
+    assert np.abs(Rg - Ro).max() <= REL * _cell_flux_scale(U, om, cells)

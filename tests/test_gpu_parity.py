@@ -464,7 +464,7 @@ def test_full_size_teno6_wavejump_sampled(teno, oracle_mod, torch_cuda):
 
 
 def test_full_size_teno5_khi_sampled(teno, oracle_mod, torch_cuda):
-    # the paper's KHI state (Sec. 5.8) on 576,738 cells
+    # the paper's KHI state (Sec. 5.7) on 576,738 cells
     _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=96)
 
 

@@ -151,3 +151,40 @@ def test_solver_needs_a_device_or_fails_cleanly(teno):
     lm = teno.Mesh(m.xy, m.tri).setup(order=3)
     with pytest.raises(teno.TenoError):
         teno.Solver(lm)
+
+
+def test_boundary_faces_and_conditions(teno, oracle_mod):
+    # boundary faces are numbered alike on both sides; bad kinds are refused
+    m = inputs.jittered_box_mesh(9, 5, 2, 1.8, 1.0)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    v, c = lm.boundary_faces()
+    v2, c2 = om.boundary_faces()
+    np.testing.assert_array_equal(v, v2)
+    np.testing.assert_array_equal(c, c2)
+    assert len(v) == 2 * (9 + 5) and lm.info().n_bface == len(v)
+    with pytest.raises(teno.TenoError, match="kind"):
+        lm.set_boundary(np.full(len(v), 4))
+    with pytest.raises(teno.TenoError, match="states"):
+        lm.set_boundary(np.full(len(v), teno.BC_PRESCRIBED))
+    lm.set_boundary(np.full(len(v), teno.BC_REFLECTIVE))
+    # an open edge on a doubly periodic mesh is still an error
+    p = inputs.jittered_periodic_mesh(8, 1)
+    with pytest.raises(teno.TenoError, match="open edge"):
+        teno.Mesh(p.xy, p.tri[:-1])
+
+
+@pytest.mark.parametrize("order", [3, 6])
+def test_box_setup_parity_with_oracle(teno, oracle_mod, order):
+    m = inputs.jittered_box_mesh(20, 12, 4, 20 / 12, 1.0)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period).setup(order=order)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    om.setup(oracle_mod.params(order=order), all_cells=False)
+    for i in range(0, m.n_cell, 5):
+        for k in range(4):
+            np.testing.assert_array_equal(lm.stencil(i, k), om.stencil(i, k))
+    for i in (0, 19, 231):
+        for k in range(4):
+            a = lm.lsq_operator(i, k)
+            b, _ = om.lsq_operator(i, k)
+            assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
