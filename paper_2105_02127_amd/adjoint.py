@@ -10,7 +10,11 @@ by a reverse-stencil gather, no atomics).
 Memory: U is checkpointed every `checkpoint_every` steps; the backward pass
 recomputes one segment at a time (its stage states, flags and, unless
 `keep_face_states` is off, the face states of every stage, which spares the
-adjoint a reconstruction per stage) and walks it backwards.
+adjoint a reconstruction per stage) and walks it backwards.  With
+`checkpoint_every=None` the forward pass keeps all of that for every step
+instead, and the backward pass recomputes nothing: about
+96 n_cell + 8 face_state_doubles * 3 bytes per step (2.5 + 15 GB for 200
+steps of TENO4 on 131,072 cells), which one GPU's HBM holds.
 """
 from __future__ import annotations
 
@@ -54,15 +58,20 @@ class RK3Rollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, U0, solver, n_steps, cfl, checkpoint_every, dts, keep_face_states=True):
-        U, dts_used, ckpts = forward_rollout(solver, U0, n_steps, cfl, dts, checkpoint_every)
-        if dts is not None:
-            dts_used = dts_used.clone()
         ctx.solver = solver
         ctx.n_steps = n_steps
         ctx.K = checkpoint_every
-        ctx.dts = dts_used
-        ctx.ckpts = ckpts
         ctx.keep = keep_face_states
+        if checkpoint_every is None:
+            U, dts_used, kept = _forward_keep_all(solver, U0, n_steps, cfl, dts, keep_face_states)
+            ctx.kept = kept
+            ctx.ckpts = None
+        else:
+            U, dts_used, ckpts = forward_rollout(solver, U0, n_steps, cfl, dts, checkpoint_every)
+            ctx.ckpts = ckpts
+        if dts is not None:
+            dts_used = dts_used.clone()
+        ctx.dts = dts_used
         ctx.mark_non_differentiable(dts_used)
         return U, dts_used
 
@@ -70,6 +79,13 @@ class RK3Rollout(torch.autograd.Function):
     def backward(ctx, grad_U, grad_dts):
         sv, n, K = ctx.solver, ctx.n_steps, ctx.K
         lam = grad_U.detach().contiguous().clone()
+        if K is None:                      # everything kept: no recompute
+            stages, flags, fs = ctx.kept
+            for s in reversed(range(n)):
+                sv.vjp_rk_step(stages[s], flags[s], ctx.dts[s:s + 1], lam, lam,
+                               face_states=None if fs is None else fs[s])
+            ctx.kept = None
+            return lam, None, None, None, None, None, None
         nc = lam.shape[0]
         dev = lam.device
         stages = torch.empty((K, 3, nc, 4), dtype=torch.float64, device=dev)
@@ -88,10 +104,31 @@ class RK3Rollout(torch.autograd.Function):
         return lam, None, None, None, None, None, None
 
 
+def _forward_keep_all(solver, U0, n_steps, cfl, dts, keep_face_states):
+    """Forward rollout that keeps every step's stage inputs, flags and (when
+    keep_face_states) face states for the backward pass."""
+    U = U0.detach().clone()
+    nc, dev = U.shape[0], U.device
+    fixed = dts is not None
+    if not fixed:
+        dts = torch.empty(n_steps, dtype=torch.float64, device=dev)
+    stages = torch.empty((n_steps, 3, nc, 4), dtype=torch.float64, device=dev)
+    flags = torch.empty((n_steps, 3, nc), dtype=torch.int16, device=dev)
+    fs = solver.empty_face_states(n_steps) if keep_face_states else None
+    for s in range(n_steps):
+        dt = dts[s:s + 1]
+        if not fixed:
+            solver.max_dt(U, cfl, dt)
+        solver.rk_step(U, dt, flags3=flags[s], stages=stages[s],
+                       face_states=None if fs is None else fs[s])
+    return U, dts, (stages, flags, fs)
+
+
 def rollout(solver, U0, n_steps, cfl=0.4, checkpoint_every=20, dts=None, keep_face_states=True):
     """Differentiable rollout: returns (U_final, dts).  keep_face_states
     trades 3 * face_state_doubles * 8 bytes per checkpointed step of device
-    memory for one reconstruction per stage of the backward pass."""
+    memory for one reconstruction per stage of the backward pass.
+    checkpoint_every=None keeps every step and recomputes nothing."""
     return RK3Rollout.apply(U0, solver, n_steps, cfl, checkpoint_every, dts, keep_face_states)
 
 

@@ -56,6 +56,27 @@ def test_rollout_gradient_matches_oracle(oracle_mod, torch_cuda):
         assert np.abs(g[:, v] - lam[:, v]).max() <= 1e-10 * np.abs(lam[:, v]).max(), v
 
 
+def test_keep_all_equals_checkpointed(torch_cuda):
+    # keeping every step (no recompute) gives the checkpointed gradient bit
+    # for bit: the recompute reproduces the forward pass exactly
+    torch = torch_cuda
+    from paper_2105_02127_amd import adjoint, teno
+    m = inputs.jittered_periodic_mesh(20, 103)
+    U0 = inputs.random_lines(m)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=5, fallback=1)
+    sv = teno.Solver(lm)
+    U0d = torch.as_tensor(U0[lm.perm], device="cuda")
+    w = torch.as_tensor(np.random.default_rng(7).normal(size=U0.shape), device="cuda")
+    grads = []
+    for K, keep in ((3, True), (None, True), (None, False)):
+        x = U0d.clone().requires_grad_(True)
+        UT, _ = adjoint.rollout(sv, x, 7, checkpoint_every=K, keep_face_states=keep)
+        (UT * w).sum().backward()
+        grads.append(x.grad.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
+
+
 def test_adjoint_workload_against_finite_differences(torch_cuda):
     torch = torch_cuda
     from paper_2105_02127_amd import adjoint, teno
