@@ -75,6 +75,7 @@ struct Mesh {
   // distinct stencil members of each tile, staged in LDS by the kernel
   int ustride = 0;              // list length per tile (largest count, rounded up)
   std::vector<int32_t> tmem;    // [n_tiles][ustride] sorted, padded with the last
+  std::vector<int32_t> tcount;  // [n_tiles] distinct members of each tile (unpadded)
   std::vector<uint16_t> slot;   // [n_tiles][rows4][16][4] position of each member in its
                                 // tile's list (packed like idx)
   std::vector<double> M;        // [n_tiles][Jp/2][kTile][2] operator entries (pairs)
@@ -89,9 +90,9 @@ struct Mesh {
   std::vector<int32_t> cell_faces;  // [n_pad][4]: sorted face of local edges 0..2;
                                     //   bit e of [3] set when the cell is that face's L
   std::vector<double> vol;          // [n_pad] |V| (1 for padding cells)
-  // reverse stencil (adjoint gather): cells i whose row r names cell j
+  // reverse member lists (adjoint gather): the tile member slots naming cell j
   std::vector<int32_t> rev_ptr; // [n_cell + 1]
-  std::vector<int32_t> rev_ent; // i * rows4*4 + r, internal ids
+  std::vector<int32_t> rev_ent; // tile * ustride + slot, by tile
 };
 
 // Stencil row order of a cell: rows 0..32 hold the three small stencils

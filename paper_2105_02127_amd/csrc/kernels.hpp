@@ -1088,23 +1088,20 @@ __global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
   }
 }
 
-// Adjoint of stencil row r of a cell: rows of a tile's 16 cells lie together
-// (512 contiguous bytes per row), so the rows that name one cell, which come
-// from its neighbourhood, sit in a few nearby tiles.
-__device__ __forceinline__ size_t dbar_index(int cell, int r, int rows4x4) {
-  return (((size_t)(cell / kTile) * rows4x4 + r) * kTile + cell % kTile) * 4;
-}
-
-// Phase 2 (one lane per (cell, variable)): transpose of the reconstruction.
-// Writes the adjoint of every stencil difference d_s = U_s - U_0 to
-// dbar (dbar_index: tile-local, each row's 16 cells together) and the cell's
-// own direct part to own[n][4].
+// Phase 2 (one wavefront per tile, one lane per (cell, variable)):
+// transpose of the reconstruction.  The adjoint of each stencil difference
+// d_s = U_s - U_0 goes to the tile's member slot of U_s, summed in LDS (one
+// accumulator per distinct member and variable, added with LDS atomics),
+// and the tile's sums are written once to tbar; the cell's own part (the
+// -U_0 of its differences and its face points) goes to own[n][4].
 struct AdjReconArgs {
   const double* __restrict__ fpbar;
   const uint16_t* __restrict__ flags;
   const double2* __restrict__ M;
-  double* __restrict__ dbar;   // [n_tiles][rows4*4][16][4]
-  double* __restrict__ own;    // [n_pad][4]
+  const int4* __restrict__ slot;  // [n_tiles][rows4][16][4] uint16 member slots
+  double* __restrict__ tbar;      // [n_tiles][ustride][4]
+  double* __restrict__ own;       // [n_pad][4]
+  int ustride;
   int n_cell, n_tiles, n_pad;
 };
 
@@ -1113,20 +1110,25 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
-  const int lane = threadIdx.x & 63;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-  if (tile >= a.n_tiles) return;
+  extern __shared__ double lds_acc[];  // 4 wavefronts x ustride x 4
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (tile >= a.n_tiles) return;  // whole wavefront leaves together
+  double* acc = lds_acc + (size_t)wave * a.ustride * 4;
+  for (int i = lane; i < 4 * a.ustride; i += 64) acc[i] = 0.0;
+  wave_lds_sync();
   const int c = lane / kLanesPerCell, v = lane % kLanesPerCell;
   const int cell = tile * kTile + c;
-  if (cell >= a.n_cell || v >= 4) return;
-  const unsigned nib = (a.flags[cell] >> (4 * v)) & 0xFu;
+  const bool live = cell < a.n_cell && v < 4;
+  const int cl = live ? cell : tile * kTile;
+  const unsigned nib = live ? ((a.flags[cl] >> (4 * v)) & 0xFu) : 0u;
   double gsum = 0.0;
   double ab[NU];
 #pragma unroll
   for (int l = 0; l < NU; ++l) ab[l] = 0.0;
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
-    const double gq = a.fpbar[((size_t)q * a.n_pad + cell) * 4 + v];
+    const double gq = live ? a.fpbar[((size_t)q * a.n_pad + cl) * 4 + v] : 0.0;
     gsum += gq;
 #pragma unroll
     for (int l = 0; l < NU; ++l) ab[l] = fma(FaceBasis<O::R, NQ>::P.v[q][l], gq, ab[l]);
@@ -1135,97 +1137,75 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   const double* __restrict__ mp =
       reinterpret_cast<const double*>(a.M + (size_t)tile * (O::JP / 2) * kTile + c);
   auto entry = [&](int j) { return mp[(size_t)(j >> 1) * (2 * kTile) + (j & 1)]; };
+  const uint16_t* __restrict__ sl =
+      reinterpret_cast<const uint16_t*>(a.slot + (size_t)tile * slot_int4(O::ROWS4));
+  auto slot_of = [&](int r) { return (int)sl[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)]; };
   const bool keepK = nib & 8u;
   const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
   double dsum = 0.0;
   // small stencils: coefficient adjoint ab[l]/cnt when kept in step two
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double wk = (!keepK && (nib & (1u << k)) && cnt > 0) ? 1.0 / (double)cnt : 0.0;
+    const bool kept = live && !keepK && (nib & (1u << k)) && cnt > 0;
+    if (kept) {
+      const double wk = 1.0 / (double)cnt;
 #pragma unroll
-    for (int s = 0; s < 11; ++s) {
-      const int r = small_row(k, s);
+      for (int s = 0; s < 11; ++s) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) d = fma(entry(k * O::SBLK + entry_in_block(5, s, l)), ab[l], d);
+        d *= wk;
+        dsum += d;
+        atomicAdd(&acc[slot_of(small_row(k, s)) * 4 + v], d);
+      }
+    }
+  }
+  if (live && keepK) {
+#pragma unroll 1
+    for (int s = 0; s < O::NL; ++s) {
       double d = 0.0;
 #pragma unroll
-      for (int l = 0; l < 5; ++l) d = fma(entry(k * O::SBLK + entry_in_block(5, s, l)), ab[l], d);
-      d *= wk;
+      for (int l = 0; l < NU; ++l) {
+        const int j = 3 * O::SBLK + entry_in_block(NU, s, l);
+        d = fma(entry(j), ab[l], d);
+      }
       dsum += d;
-      a.dbar[dbar_index(cell, r, O::ROWS4 * 4) + v] = d;
+      atomicAdd(&acc[slot_of(large_row(s)) * 4 + v], d);
     }
   }
-  const double wK = keepK ? 1.0 : 0.0;
-#pragma unroll 1
-  for (int s = 0; s < O::NL; ++s) {
-    double d = 0.0;
-#pragma unroll
-    for (int l = 0; l < NU; ++l) {
-      const int j = 3 * O::SBLK + entry_in_block(NU, s, l);
-      d = fma(entry(j), ab[l], d);
-    }
-    d *= wK;
-    dsum += d;
-    a.dbar[dbar_index(cell, 33 + s, O::ROWS4 * 4) + v] = d;
-  }
-  a.own[(size_t)cell * 4 + v] = gsum - dsum;
+  if (live) a.own[(size_t)cell * 4 + v] = gsum - dsum;
+  wave_lds_sync();
+  double* __restrict__ tb = a.tbar + (size_t)tile * a.ustride * 4;
+  for (int i = lane; i < 4 * a.ustride; i += 64) tb[i] = acc[i];
 }
 
-// Phase 3 (four lanes per cell): U_bar[j] = own[j] + the adjoints of every
-// stencil row naming j (reverse list rev_ptr[j] .. rev_ptr[j+1]-1).  Lane q
-// of the cell's quad sums entries q, q+4, ... in list order, fetching its
-// entries and their rows GB at a time (the walk is a chain of dependent
-// loads); the quad then adds its four partial sums in lane order.  Fixed
-// order, no atomics.  Then out = U_bar + beta * extra (extra nullable).
+// Phase 3 (four lanes per cell, lane q = variable q): U_bar[j] = own[j] +
+// the tile sums of every tile member slot naming j (reverse list rev_ptr[j]
+// .. rev_ptr[j+1]-1, by tile), in list order: no atomics.  Then out = U_bar
+// + beta * extra (extra nullable).
 __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ own,
-                                                    const double* __restrict__ dbar,
+                                                    const double* __restrict__ tbar,
                                                     const int32_t* __restrict__ rev_ptr,
-                                                    const int32_t* __restrict__ rev_ent, int rows4x4,
+                                                    const int32_t* __restrict__ rev_ent,
                                                     int n_cell, const double* extra, double beta,
                                                     double* out) {
   const int gid = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   const int j = gid >> 2, q = gid & 3;
-  // whole quads leave together (n_cell cells use 4 * n_cell lanes)
   if (j >= n_cell) return;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
   const int b = rev_ptr[j], e = rev_ptr[j + 1];
-  constexpr int GB = 4;
-  auto row_of = [&](int ent) {
-    const int i = ent / rows4x4, r = ent - i * rows4x4;
-    return reinterpret_cast<const double2*>(dbar + dbar_index(i, r, rows4x4));
-  };
-  int t = b + q;
-  for (; t + 4 * (GB - 1) < e; t += 4 * GB) {
-    int ent[GB];
-#pragma unroll
-    for (int k = 0; k < GB; ++k) ent[k] = rev_ent[t + 4 * k];
-    double2 x[GB], y[GB];
-#pragma unroll
-    for (int k = 0; k < GB; ++k) {
-      const double2* d2 = row_of(ent[k]);
-      x[k] = d2[0];
-      y[k] = d2[1];
-    }
-#pragma unroll
-    for (int k = 0; k < GB; ++k) {
-      s[0] += x[k].x;
-      s[1] += x[k].y;
-      s[2] += y[k].x;
-      s[3] += y[k].y;
-    }
+  double s = 0.0;
+  int t = b;
+  for (; t + 3 < e; t += 4) {
+    const int e0 = rev_ent[t], e1 = rev_ent[t + 1], e2 = rev_ent[t + 2], e3 = rev_ent[t + 3];
+    const double x0 = tbar[(size_t)e0 * 4 + q], x1 = tbar[(size_t)e1 * 4 + q];
+    const double x2 = tbar[(size_t)e2 * 4 + q], x3 = tbar[(size_t)e3 * 4 + q];
+    s += x0;
+    s += x1;
+    s += x2;
+    s += x3;
   }
-  for (; t < e; t += 4) {
-    const double2* d2 = row_of(rev_ent[t]);
-    const double2 x = d2[0], y = d2[1];
-    s[0] += x.x;
-    s[1] += x.y;
-    s[2] += y.x;
-    s[3] += y.y;
-  }
-  double tot[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-    tot[c] = ((quad_bcast<0>(s[c]) + quad_bcast<1>(s[c])) + quad_bcast<2>(s[c])) + quad_bcast<3>(s[c]);
-  // lane q finishes variable q
-  double v = own[(size_t)j * 4 + q] + pick4(tot[0], tot[1], tot[2], tot[3], q);
+  for (; t < e; ++t) s += tbar[(size_t)rev_ent[t] * 4 + q];
+  double v = own[(size_t)j * 4 + q] + s;
   if (extra) v = v + beta * extra[(size_t)j * 4 + q];
   out[(size_t)j * 4 + q] = v;
 }

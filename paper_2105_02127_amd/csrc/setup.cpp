@@ -719,26 +719,30 @@ int mesh_setup(Mesh& m, const teno_params& p) {
                                      "); keep the default cell reordering");
     m.ustride = (umax.load() + 15) / 16 * 16;
     m.tmem.assign((size_t)m.n_tiles * m.ustride, 0);
+    m.tcount.assign(m.n_tiles, 0);
     for (int tile = 0; tile < m.n_tiles; ++tile) {
       const auto& u = lists[tile];
+      m.tcount[tile] = (int32_t)u.size();
       for (int k = 0; k < m.ustride; ++k)
         m.tmem[(size_t)tile * m.ustride + k] = u.empty() ? 0 : u[std::min<size_t>(k, u.size() - 1)];
     }
   }
 
-  // ---- reverse stencil lists for the adjoint gather ----
-  const int R4 = d.rows4 * 4;
+  // ---- reverse member lists for the adjoint gather: the (tile, slot)
+  //      entries naming each cell, by tile ----
   m.rev_ptr.assign(nc + 1, 0);
-  for (int t = 0; t < nc; ++t)
-    for (int r = 0; r < d.rows; ++r) m.rev_ptr[m.idx[packed_idx_index(m, t, r)] + 1]++;
+  for (int tile = 0; tile < m.n_tiles; ++tile)
+    for (int k = 0; k < m.tcount[tile]; ++k) m.rev_ptr[m.tmem[(size_t)tile * m.ustride + k] + 1]++;
   for (int t = 0; t < nc; ++t) m.rev_ptr[t + 1] += m.rev_ptr[t];
-  m.rev_ent.assign(m.rev_ptr[nc], 0);
-  std::vector<int32_t> fill(m.rev_ptr.begin(), m.rev_ptr.end() - 1);
-  for (int t = 0; t < nc; ++t)
-    for (int r = 0; r < d.rows; ++r) {
-      int j = m.idx[packed_idx_index(m, t, r)];
-      m.rev_ent[fill[j]++] = t * R4 + r;
-    }
+  m.rev_ent.assign(std::max<int32_t>(1, m.rev_ptr[nc]), 0);
+  {
+    std::vector<int32_t> fill(m.rev_ptr.begin(), m.rev_ptr.end() - 1);
+    for (int tile = 0; tile < m.n_tiles; ++tile)
+      for (int k = 0; k < m.tcount[tile]; ++k) {
+        const int j = m.tmem[(size_t)tile * m.ustride + k];
+        m.rev_ent[fill[j]++] = tile * m.ustride + k;
+      }
+  }
   m.ready = true;
   return TENO_OK;
 }

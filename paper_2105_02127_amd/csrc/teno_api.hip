@@ -90,7 +90,7 @@ struct teno_solver {
   int32_t* rev_ent = nullptr;
   double* fp = nullptr;
   double* fpbar = nullptr;
-  double* dbar = nullptr;
+  double* tbar = nullptr;   // adjoint: per-tile member sums [n_tiles][ustride][4]
   double* own = nullptr;
   double* W1 = nullptr;
   double* W2 = nullptr;
@@ -297,7 +297,9 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   ra.fpbar = s->fpbar;
   ra.flags = flags;
   ra.M = s->M;
-  ra.dbar = s->dbar;
+  ra.slot = s->slot;
+  ra.tbar = s->tbar;
+  ra.ustride = s->ustride;
   ra.own = s->own;
   ra.n_cell = s->n_cell;
   ra.n_tiles = s->n_tiles;
@@ -308,9 +310,9 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
     rc = timed(s, 3, st, [&]() {
       hipLaunchKernelGGL((k_adj_face<decltype(NQ)::value>), dim3(cblocks), dim3(256), 0, st, fa);
       hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
-                         dim3(256), 0, st, ra);
-      hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->dbar,
-                         s->rev_ptr, s->rev_ent, s->d.rows4 * 4, s->n_cell, extra, beta, out);
+                         dim3(256), (size_t)4 * s->ustride * 4 * sizeof(double), st, ra);
+      hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->tbar,
+                         s->rev_ptr, s->rev_ent, s->n_cell, extra, beta, out);
     });
   });
   return rc;
@@ -535,7 +537,7 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
   A(s->rev_ent, std::max<size_t>(1, m.rev_ent.size()));
   A(s->fp, (size_t)3 * m.d.nq * np * 4);
   A(s->fpbar, (size_t)3 * m.d.nq * np * 4);
-  A(s->dbar, (size_t)m.d.rows4 * 4 * np * 4);
+  A(s->tbar, (size_t)m.n_tiles * m.ustride * 4);
   A(s->own, np * 4);
   A(s->W1, nc * 4);
   A(s->W2, nc * 4);
