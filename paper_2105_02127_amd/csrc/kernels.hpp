@@ -1010,82 +1010,84 @@ __global__ __launch_bounds__(256) void k_dt_final(const double* __restrict__ par
 // ---------------------------------------------------------------------------
 // adjoint of the residual (selection frozen)
 // ---------------------------------------------------------------------------
-// Phase 1 (one lane per cell): adjoint of the cell's own face-point states.
-// Face f gets Phi_bar = lam_R/|V_R| - lam_L/|V_L| (scaled by `scale`); each
-// side differentiates the flux with respect to its own state only.
-struct AdjArgs {
-  const double* __restrict__ fp;
-  const int4* __restrict__ nbinfo;
-  const double* __restrict__ geo;
+// Phase 1 (one lane per (face, side)): adjoint of the face-point states.
+// Face f gets Phi_bar = lam_R/|V_R| - lam_L/|V_L| (scaled by `scale`); the
+// lane takes the HLL Jacobian of its face with respect to the state of one
+// side only (dual numbers seeded on that argument at compile time) and
+// writes that side's face-point adjoints.  Blocks hold one side each, so no
+// wavefront mixes the two seedings (a per-cell loop over its edges mixes L
+// and R sides in a wavefront and evaluates the dual HLL under both
+// branches).
+struct AdjFaceArgs {
+  const double* __restrict__ fp;      // [3 nq][n_pad][4]
+  const int4* __restrict__ fcell;     // [n_face]: L, R, eL | eR << 2
+  const double2* __restrict__ fgeo;   // [n_face][2]: (nx, ny), (|A|, 0)
+  const double* __restrict__ vol;     // [n_pad]
   const double* __restrict__ lam;
-  const double* scale_dev;  // device scalar multiplying lam (nullable = 1)
+  const double* scale_dev;            // device scalar multiplying lam (nullable = 1)
   double scale;
-  double* __restrict__ fpbar;  // [3 nq][n_pad][4]
+  double* __restrict__ fpbar;         // [3 nq][n_pad][4]
   double gamma;
-  int n_cell, n_pad;
+  int n_face, n_pad;
 };
 
-template <int NQ>
-__global__ __launch_bounds__(256) void k_adj_face(AdjArgs a) {
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (t >= a.n_cell) return;
-  const int4 nb = a.nbinfo[t];
-  const double* g = a.geo + (size_t)t * 10;
+template <int NQ, int SIDE>
+__device__ __forceinline__ void adj_face_side(const AdjFaceArgs& a, int f) {
+  const int4 fc = a.fcell[f];
+  const double2 nrm = a.fgeo[2 * (size_t)f], len = a.fgeo[2 * (size_t)f + 1];
+  const int L = fc.x, R = fc.y, eL = fc.z & 3, eR = (fc.z >> 2) & 3;
   const double sc = a.scale * (a.scale_dev ? *a.scale_dev : 1.0);
+  const double aL = a.vol[L], aR = a.vol[R];
+  double pb[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    pb[c] = sc * (a.lam[(size_t)R * 4 + c] / aR - a.lam[(size_t)L * 4 + c] / aL);
   const double2* fp2 = reinterpret_cast<const double2*>(a.fp);
-  const double ai = g[9];
-  double li[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) li[c] = a.lam[(size_t)t * 4 + c];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int j = e == 0 ? nb.x : (e == 1 ? nb.y : nb.z);
-    const int ej = (nb.w >> (2 * e)) & 3;
-    const bool isL = (nb.w >> (6 + e)) & 1;
-    const double nx = g[3 * e], ny = g[3 * e + 1], len = g[3 * e + 2];
-    const double aj = a.geo[(size_t)j * 10 + 9];
-    double pb[4];
+  for (int k = 0; k < NQ; ++k) {
+    const int qL = eL * NQ + k, qR = eR * NQ + NQ - 1 - k;
+    const size_t oL = ((size_t)qL * a.n_pad + L) * 2, oR = ((size_t)qR * a.n_pad + R) * 2;
+    const double2 l0 = fp2[oL], l1 = fp2[oL + 1], r0 = fp2[oR], r1 = fp2[oR + 1];
+    const double vl[4] = {l0.x, l0.y, l1.x, l1.y}, vr[4] = {r0.x, r0.y, r1.x, r1.y};
+    Dual<4> uL[4], uR[4], F[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double lj = a.lam[(size_t)j * 4 + c];
-      const double lL = isL ? li[c] : lj, lR = isL ? lj : li[c];
-      const double aL = isL ? ai : aj, aR = isL ? aj : ai;
-      pb[c] = sc * (lR / aR - lL / aL);
-    }
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int qi = e * NQ + (isL ? k : NQ - 1 - k);
-      const int qj = ej * NQ + (isL ? NQ - 1 - k : k);
-      const size_t oi = ((size_t)qi * a.n_pad + t) * 2;
-      const size_t oj = ((size_t)qj * a.n_pad + j) * 2;
-      const double2 i0 = fp2[oi], i1 = fp2[oi + 1];
-      const double2 j0 = fp2[oj], j1 = fp2[oj + 1];
-      const double own[4] = {i0.x, i0.y, i1.x, i1.y};
-      const double oth[4] = {j0.x, j0.y, j1.x, j1.y};
-      Dual<4> o[4], p[4], F[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        o[c].v = own[c];
-        p[c].v = oth[c];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          o[c].d[d] = (c == d) ? 1.0 : 0.0;
-          p[c].d[d] = 0.0;
-        }
-      }
-      if (isL) hll<Dual<4>>(o, p, nx, ny, a.gamma, F);
-      else hll<Dual<4>>(p, o, nx, ny, a.gamma, F);
-      const double w = len * FaceRule<NQ>::w[k];
-      double* out = a.fpbar + ((size_t)qi * a.n_pad + t) * 4;
+      uL[c].v = vl[c];
+      uR[c].v = vr[c];
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) s = fma(pb[c], F[c].d[d], s);
-        out[d] = w * s;
+        uL[c].d[d] = (SIDE == 0 && c == d) ? 1.0 : 0.0;
+        uR[c].d[d] = (SIDE == 1 && c == d) ? 1.0 : 0.0;
       }
     }
+    hll<Dual<4>>(uL, uR, nrm.x, nrm.y, a.gamma, F);
+    const double w = len.x * FaceRule<NQ>::w[k];
+    const int q = SIDE == 0 ? qL : qR, cell = SIDE == 0 ? L : R;
+    double* out = a.fpbar + ((size_t)q * a.n_pad + cell) * 4;
+    double o[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s = fma(pb[c], F[c].d[d], s);
+      o[d] = w * s;
+    }
+    reinterpret_cast<double2*>(out)[0] = make_double2(o[0], o[1]);
+    reinterpret_cast<double2*>(out)[1] = make_double2(o[2], o[3]);
   }
+}
+
+// Grid: 2 * nfb blocks, the first nfb for the L sides, the rest for the R sides.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_adj_face_sides(AdjFaceArgs a, int nfb) {
+  const int side = blockIdx.x >= (unsigned)nfb;
+  const int b = blockIdx.x - side * nfb;
+  const int f = xcd_remap(b, nfb) * 256 + threadIdx.x;
+  if (f >= a.n_face) return;
+  if (side == 0)
+    adj_face_side<NQ, 0>(a, f);
+  else
+    adj_face_side<NQ, 1>(a, f);
 }
 
 // Phase 2 (one wavefront per tile, one lane per (cell, variable)):

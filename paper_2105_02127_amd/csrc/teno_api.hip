@@ -281,18 +281,19 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
     rc = launch_reconstruct(s, U, const_cast<uint16_t*>(flags), true, st);
     if (rc) return rc;
   }
-  AdjArgs fa;
-  fa.fp = fp_in ? fp_in : s->fp;
-  fa.nbinfo = s->nbinfo;
-  fa.geo = s->geo;
-  fa.lam = lam;
-  fa.scale_dev = scale_dev;
-  fa.scale = scale;
-  fa.fpbar = s->fpbar;
-  fa.gamma = s->prm.gamma;
-  fa.n_cell = s->n_cell;
-  fa.n_pad = s->n_pad;
-  const int cblocks = (s->n_cell + 255) / 256;
+  AdjFaceArgs ff;
+  ff.fp = fp_in ? fp_in : s->fp;
+  ff.fcell = s->fcell;
+  ff.fgeo = s->fgeo;
+  ff.vol = s->vol;
+  ff.lam = lam;
+  ff.scale_dev = scale_dev;
+  ff.scale = scale;
+  ff.fpbar = s->fpbar;
+  ff.gamma = s->prm.gamma;
+  ff.n_face = s->n_face;
+  ff.n_pad = s->n_pad;
+  const int fblocks = (s->n_face + 255) / 256;
   AdjReconArgs ra;
   ra.fpbar = s->fpbar;
   ra.flags = flags;
@@ -308,7 +309,8 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   const int qblocks = (int)(((int64_t)s->n_cell * 4 + 255) / 256);
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 3, st, [&]() {
-      hipLaunchKernelGGL((k_adj_face<decltype(NQ)::value>), dim3(cblocks), dim3(256), 0, st, fa);
+      hipLaunchKernelGGL((k_adj_face_sides<decltype(NQ)::value>), dim3(2 * fblocks), dim3(256), 0,
+                         st, ff, fblocks);
       hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
                          dim3(256), (size_t)4 * s->ustride * 4 * sizeof(double), st, ra);
       hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->tbar,
