@@ -508,10 +508,11 @@ __device__ __forceinline__ void large_part(const ReconArgs& a, bool frozen, unsi
 // b2 = b1 |u|^2 / 2).  A mean that is not physical keeps the conservative
 // variables (identity rows).  The two are formed apart, each when needed,
 // to keep fewer registers live.
+// The normal-independent part of the projection state, formed once per cell.
 struct CharState {
-  double ux, uy, q2, c, H, un, ut;
+  double ux, uy, q2, c, ic, H, b1, b2;
 };
-__device__ __forceinline__ CharState char_state(double u0, double nx, double ny, double g) {
+__device__ __forceinline__ CharState char_state(double u0, double g) {
   const double rho = quad_bcast<0>(u0), mx = quad_bcast<1>(u0), my = quad_bcast<2>(u0),
                en = quad_bcast<3>(u0);
   CharState S;
@@ -521,43 +522,43 @@ __device__ __forceinline__ CharState char_state(double u0, double nx, double ny,
   S.q2 = S.ux * S.ux + S.uy * S.uy;
   const double p = (g - 1.0) * (en - 0.5 * rho * S.q2);
   S.c = sqrt(g * p * ir);
+  S.ic = 1.0 / S.c;
   S.H = (en + p) * ir;
-  S.un = S.ux * nx + S.uy * ny;
-  S.ut = S.uy * nx - S.ux * ny;
+  S.b1 = (g - 1.0) * S.ic * S.ic;
+  S.b2 = 0.5 * S.q2 * S.b1;
   return S;
 }
 
-__device__ __forceinline__ void char_lrow(double u0, double nx, double ny, double g, bool ok, int v,
+__device__ __forceinline__ void char_lrow(const CharState& S, double nx, double ny, bool ok, int v,
                                           double (&lrow)[4]) {
   if (!ok) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) lrow[j] = (j == v) ? 1.0 : 0.0;
     return;
   }
-  const CharState S = char_state(u0, nx, ny, g);
-  const double ic = 1.0 / S.c;
-  const double b1 = (g - 1.0) * ic * ic, b2 = 0.5 * S.q2 * b1;
+  const double un = S.ux * nx + S.uy * ny, ut = S.uy * nx - S.ux * ny;
+  const double b1 = S.b1, b2 = S.b2, ic = S.ic;
   const double L[4][4] = {
-      {0.5 * (b2 + S.un * ic), -0.5 * (b1 * S.ux + nx * ic), -0.5 * (b1 * S.uy + ny * ic), 0.5 * b1},
+      {0.5 * (b2 + un * ic), -0.5 * (b1 * S.ux + nx * ic), -0.5 * (b1 * S.uy + ny * ic), 0.5 * b1},
       {1.0 - b2, b1 * S.ux, b1 * S.uy, -b1},
-      {-S.ut, -ny, nx, 0.0},
-      {0.5 * (b2 - S.un * ic), -0.5 * (b1 * S.ux - nx * ic), -0.5 * (b1 * S.uy - ny * ic), 0.5 * b1}};
+      {-ut, -ny, nx, 0.0},
+      {0.5 * (b2 - un * ic), -0.5 * (b1 * S.ux - nx * ic), -0.5 * (b1 * S.uy - ny * ic), 0.5 * b1}};
 #pragma unroll
   for (int j = 0; j < 4; ++j) lrow[j] = pick4(L[0][j], L[1][j], L[2][j], L[3][j], v);
 }
 
-__device__ __forceinline__ void char_rrow(double u0, double nx, double ny, double g, bool ok, int v,
+__device__ __forceinline__ void char_rrow(const CharState& S, double nx, double ny, bool ok, int v,
                                           double (&rrow)[4]) {
   if (!ok) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) rrow[j] = (j == v) ? 1.0 : 0.0;
     return;
   }
-  const CharState S = char_state(u0, nx, ny, g);
+  const double un = S.ux * nx + S.uy * ny, ut = S.uy * nx - S.ux * ny;
   const double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
                           {S.ux - S.c * nx, S.ux, -ny, S.ux + S.c * nx},
                           {S.uy - S.c * ny, S.uy, nx, S.uy + S.c * ny},
-                          {S.H - S.c * S.un, 0.5 * S.q2, S.ut, S.H + S.c * S.un}};
+                          {S.H - S.c * un, 0.5 * S.q2, ut, S.H + S.c * un}};
 #pragma unroll
   for (int j = 0; j < 4; ++j) rrow[j] = pick4(R[0][j], R[1][j], R[2][j], R[3][j], v);
 }
@@ -608,16 +609,32 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
     SmallPart<CW> sp;
     {
       double lrow[4];
-      char_lrow(u0, nx, ny, a.gamma, avg_ok, v, lrow);
+      char_lrow(char_state(u0, a.gamma), nx, ny, avg_ok, v, lrow);
 #pragma unroll
       for (int l = 0; l < NU; ++l) wK[l] = quad_dot(lrow, aK[l]);
-      auto proj = [&](int k, int l) { return quad_dot(lrow, as[k][l]); };
-      small_part<CW>(a, false, 8u, proj, proj, sp);
+      // The small stencils' projected coefficients are held for the
+      // indicators and the combination where that keeps the kernel's waves
+      // per SIMD (CWENO, orders 3 and 5); for TENO at orders 4 and 6 holding
+      // them costs a wave per SIMD (120 -> 134, 164 -> 178 VGPRs) and
+      // projecting them twice measured faster.
+      constexpr bool hold = CW || P == 3 || P == 5;
+      if constexpr (!hold) {
+        auto proj = [&](int k, int l) { return quad_dot(lrow, as[k][l]); };
+        small_part<CW>(a, false, 8u, proj, proj, sp);
+      } else {
+        double ws[3][5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 5; ++l) ws[k][l] = quad_dot(lrow, as[k][l]);
+        auto held = [&](int k, int l) { return ws[k][l]; };
+        small_part<CW>(a, false, 8u, held, held, sp);
+      }
     }
     unsigned nib = 0u;
     large_part<P, CW>(a, false, 8u, sp, wK, ab, nib, ties);
     double rrow[4];
-    char_rrow(u0, nx, ny, a.gamma, avg_ok, v, rrow);
+    char_rrow(char_state(u0, a.gamma), nx, ny, avg_ok, v, rrow);
     const double* __restrict__ fb = &FaceBasis<O::R, NQ>::P.v[e * NQ][0];
 #pragma unroll
     for (int kq = 0; kq < NQ; ++kq) {
