@@ -2,8 +2,9 @@
  * teno.h -- C ABI of libteno: the per-cell, per-Runge-Kutta-stage residual of
  * the unstructured-mesh finite-volume TENO scheme (Ji, Liang & Fu, "A class of
  * new high-order finite-volume TENO schemes for hyperbolic conservation laws
- * with unstructured meshes") for the 2D Euler equations on periodic triangle
- * meshes, in FP64, on AMD Instinct MI355X (gfx950).
+ * with unstructured meshes") for the 2D Euler equations on triangle meshes
+ * (periodic, or with transmissive, reflective and prescribed boundaries), in
+ * FP64, on AMD Instinct MI355X (gfx950).
  *
  * Conventions for every call
  *  - Return value: TENO_OK (0) or a negative teno_status; teno_last_error()
@@ -214,7 +215,9 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
 
 /* Adjoint of the residual with the selection frozen to `flags`:
  * U_bar = (dR/dU)^T lam.  The reconstruction is linear in U for fixed
- * selection, so this is exact wherever the HLL flux is differentiable. */
+ * selection, so this is exact wherever the HLL flux is differentiable.
+ * TENO_EARG for CWENO, characteristic variables or a mesh with boundary
+ * faces (as for teno_vjp_rk_step). */
 int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
                       double* U_bar, void* stream);
 
@@ -263,7 +266,8 @@ typedef struct teno_batch_tuning {
  * them runs as persistent launches over a shared work list: per stage one
  * reconstruction launch (or one per order, see tuning) over (mesh, tile)
  * items and one flux/update launch over (mesh, 64-cell) items.  The solvers
- * must outlive the batch; their workspaces are reused. */
+ * must outlive the batch; their workspaces are reused.  TENO_EARG for CWENO,
+ * characteristic variables or meshes with boundary faces. */
 int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out);
 
 int teno_batch_set_tuning(teno_batch* b, const teno_batch_tuning* t);
