@@ -39,6 +39,8 @@ from each boundary face's midpoint:
   * ``sod_x``: Sod's shock tube along x on [0, 1] x [0, Ly] (left state
     (1, 0, 1), right state (0.125, 0, 0.1), jump at x = 0.5), transmissive
     ends and reflective side walls.
+  * ``shu_osher``: the paper's shock-density wave interaction (Sec. 5.5)
+    along x on [0, 10] x [0, Ly], post-shock inflow on the left.
 """
 from __future__ import annotations
 
@@ -286,6 +288,30 @@ def sod_x(mesh: MeshData) -> np.ndarray:
     return conservative(np.where(left, 1.0, 0.125), 0.0, 0.0, np.where(left, 1.0, 0.1))
 
 
+SHU_OSHER_LEFT = (3.857, 2.629, 0.0, 10.333)
+
+
+def shu_osher(mesh: MeshData) -> np.ndarray:
+    """The shock-density wave interaction of the paper (Sec. 5.5) along x on
+    [0, 10] x [0, Ly]: (3.857, 2.629, 10.333) for x < 1, (1 + 0.2 sin(5(x -
+    5)), 0, 1) after it, at cell centroids."""
+    x = centroids(mesh, wrap=False)[:, 0]
+    left = x < 1.0
+    rho = np.where(left, SHU_OSHER_LEFT[0], 1.0 + 0.2 * np.sin(5.0 * (x - 5.0)))
+    return conservative(rho, np.where(left, SHU_OSHER_LEFT[1], 0.0), 0.0,
+                        np.where(left, SHU_OSHER_LEFT[3], 1.0))
+
+
+def shu_osher_boundary(mesh: MeshData, verts: np.ndarray):
+    """Post-shock inflow on the left, transmissive right, reflective side walls."""
+    _, side = face_sides(mesh, verts)
+    kind = np.full(len(verts), BC_REFLECTIVE, dtype=np.int32)
+    kind[side == 0] = BC_PRESCRIBED
+    kind[side == 1] = BC_TRANSMISSIVE
+    state = np.tile(conservative(*SHU_OSHER_LEFT), (len(verts), 1))
+    return kind, np.ascontiguousarray(state)
+
+
 def tube_boundary(mesh: MeshData, verts: np.ndarray):
     """Transmissive ends (left, right), reflective side walls."""
     _, side = face_sides(mesh, verts)
@@ -332,6 +358,8 @@ def make_state(mesh: MeshData, ic: str) -> np.ndarray:
         return double_mach(mesh)
     if ic == "sod_x":
         return sod_x(mesh)
+    if ic == "shu_osher":
+        return shu_osher(mesh)
     raise ValueError(ic)
 
 

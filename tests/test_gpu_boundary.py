@@ -206,3 +206,37 @@ def test_full_size_double_mach_sampled(teno, oracle_mod, torch_cuda):
     Ro, _ = om.residual_cells(U, cells)
     Rg = R.cpu().numpy()[inv[cells]]
     assert np.abs(Rg - Ro).max() <= REL * _cell_flux_scale(U, om, cells)
+
+
+@pytest.mark.parametrize("ic,order", [("sod_x", 3), ("shu_osher", 5)])
+def test_tubes_match_oracle(teno, oracle_mod, torch_cuda, ic, order):
+    # the paper's tube problems (Sec. 5.4, 5.5) on a jittered 10:1 box: three
+    # RK steps against the oracle, boundary conditions included
+    torch = torch_cuda
+    lx = 10.0 if ic == "shu_osher" else 1.0
+    m = inputs.jittered_box_mesh(60, 6, 31, lx, lx / 10.0)
+    print(f"[tube] {ic} order={order} cells={m.n_cell}", flush=True)
+    U = inputs.make_state(m, ic)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    verts, _ = lm.boundary_faces()
+    if ic == "shu_osher":
+        kind, state = inputs.shu_osher_boundary(m, verts)
+    else:
+        kind, state = inputs.tube_boundary(m, verts)
+    lm.set_boundary(kind, state)
+    om.set_boundary(kind, state)
+    lm.setup(order=order, fallback=1)
+    om.setup(oracle_mod.params(order=order, fallback=1))
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    Ud = torch.as_tensor(U[perm], device="cuda")
+    Uo = U.copy()
+    for _ in range(3):
+        dto = om.dt(Uo, 0.4)
+        Uo = om.rk_step(Uo, dto)["U"]
+        sv.rk_step(Ud, torch.full((1,), dto, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    got = np.empty_like(Uo)
+    got[perm] = Ud.cpu().numpy()
+    _assert_states(got, Uo, f"{ic} after 3 steps")
