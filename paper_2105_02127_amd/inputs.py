@@ -41,6 +41,11 @@ from each boundary face's midpoint:
     ends and reflective side walls.
   * ``shu_osher``: the paper's shock-density wave interaction (Sec. 5.5)
     along x on [0, 10] x [0, Ly], post-shock inflow on the left.
+
+Disc meshes (``disc_mesh``): rings of points about a centre, jittered inside,
+triangulated by Delaunay; every boundary face is transmissive (the library's
+default).  ``ep01`` and ``ep02`` are the paper's explosion problems (Sec. 5.6)
+on the unit disc about (1, 1).
 """
 from __future__ import annotations
 
@@ -237,6 +242,41 @@ def kelvin_helmholtz(mesh: MeshData) -> np.ndarray:
 # states and boundary conditions on meshes with open sides
 # ---------------------------------------------------------------------------
 BC_TRANSMISSIVE, BC_REFLECTIVE, BC_PRESCRIBED = 1, 2, 3
+def disc_mesh(h: float, seed: int, radius: float = 1.0, center=(1.0, 1.0),
+              jitter: float = 0.2) -> MeshData:
+    """Jittered Delaunay triangulation of a disc with open sides.
+
+    Points: the centre, then rings k = 1..K at radius k R / K with
+    K = round(R / (h sqrt(3) / 2)) and round(2 pi r / h) points each (at least
+    6), spaced evenly from a random phase; all but the outer ring are moved by
+    U[-jitter h, jitter h] on both axes, the outer ring stays on the circle.
+    The draws come from ``np.random.default_rng(seed)`` in that order (ring
+    phases, then the jitter).  Triangles are scipy's Delaunay simplices,
+    turned counter-clockwise."""
+    from scipy.spatial import Delaunay
+    if not h > 0.0 or h > radius:
+        raise ValueError("need 0 < h <= radius")
+    rng = np.random.default_rng(seed)
+    k_rings = max(1, round(radius / (h * math.sqrt(3.0) / 2.0)))
+    rings = [np.zeros((1, 2))]
+    for k in range(1, k_rings + 1):
+        r = radius * k / k_rings
+        n = max(6, round(2.0 * math.pi * r / h))
+        th = 2.0 * math.pi * (np.arange(n) + rng.uniform(0.0, 1.0)) / n
+        rings.append(np.stack([r * np.cos(th), r * np.sin(th)], 1))
+    xy = np.concatenate(rings)
+    n_in = len(xy) - len(rings[-1])
+    xy[:n_in] += rng.uniform(-jitter * h, jitter * h, size=(n_in, 2))
+    xy += np.asarray(center, dtype=np.float64)
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    a = xy[tri]
+    cw = ((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
+          - (a[:, 2, 0] - a[:, 0, 0]) * (a[:, 1, 1] - a[:, 0, 1])) < 0.0
+    tri[cw] = tri[cw][:, [0, 2, 1]]
+    return MeshData(n=k_rings, xy=np.ascontiguousarray(xy), tri=np.ascontiguousarray(tri),
+                    period=(0.0, 0.0), seed=seed, rng=rng)
+
+
 DMR_PRE = (1.4, 0.0, 0.0, 1.0)
 DMR_POST = (8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
 
@@ -319,6 +359,23 @@ def tube_boundary(mesh: MeshData, verts: np.ndarray):
     return kind, None
 
 
+EXPLOSIONS = {
+    # (inside r <= 0.5, outside) as (rho, u, v, p)
+    "ep01": ((1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.1)),
+    "ep02": ((1.0, 0.0, 0.0, 2.0), (1.0, 0.0, 0.0, 1.0)),
+}
+
+
+def explosion(mesh: MeshData, which: str = "ep01") -> np.ndarray:
+    """The paper's 2D explosion problems (Sec. 5.6) on the disc of radius 1
+    about (1, 1): one state inside the circle of radius 0.5 about the centre,
+    another outside, at cell centroids."""
+    inner, outer = EXPLOSIONS[which]
+    x = centroids(mesh, wrap=False) - 1.0
+    s = np.where(((x * x).sum(1) <= 0.25)[:, None], np.array(inner), np.array(outer))
+    return conservative(s[:, 0], s[:, 1], s[:, 2], s[:, 3])
+
+
 def disc_mask(mesh: MeshData, center, radius: float) -> np.ndarray:
     """Cells whose centroid lies within `radius` of `center` (periodic distance)."""
     x = centroids(mesh, wrap=True)
@@ -342,6 +399,9 @@ WORKLOADS = {
     # the paper's DMR timing workload at its size (369,800 ~ 369,794 triangles)
     7: dict(name="teno5_dmr_860x215", order=5, n=860, ny=215, lx=4.0, ly=1.0, seed=7,
             ic="double_mach", steps=100),
+    # the paper's explosion problems at h = 1/50 (18,218 ~ 18,464 triangles)
+    8: dict(name="teno5_ep01_h50", order=5, h=1.0 / 50.0, seed=8, ic="ep01", steps=100),
+    9: dict(name="teno5_ep02_h50", order=5, h=1.0 / 50.0, seed=9, ic="ep02", steps=100),
 }
 
 
@@ -360,6 +420,8 @@ def make_state(mesh: MeshData, ic: str) -> np.ndarray:
         return sod_x(mesh)
     if ic == "shu_osher":
         return shu_osher(mesh)
+    if ic in EXPLOSIONS:
+        return explosion(mesh, ic)
     raise ValueError(ic)
 
 
@@ -368,7 +430,11 @@ def make_workload(key: int, n: int | None = None):
     w = dict(WORKLOADS[key])
     if n is not None:
         w["n"] = n
-    if "ny" in w:
+    if "h" in w:
+        if n is not None:
+            w["h"] = 1.0 / n
+        mesh = disc_mesh(w["h"], w["seed"])
+    elif "ny" in w:
         if n is not None:
             w["ny"] = max(2, round(n * w["ly"] / w["lx"]))
         mesh = jittered_box_mesh(w["n"], w["ny"], w["seed"], w["lx"], w["ly"])

@@ -240,3 +240,31 @@ def test_tubes_match_oracle(teno, oracle_mod, torch_cuda, ic, order):
     got = np.empty_like(Uo)
     got[perm] = Ud.cpu().numpy()
     _assert_states(got, Uo, f"{ic} after 3 steps")
+
+
+@pytest.mark.parametrize("key,order,variant,characteristic", [
+    (8, 3, 0, 0), (8, 5, 0, 0), (9, 4, 0, 0), (9, 6, 0, 0), (8, 5, 2, 0), (9, 5, 0, 1)])
+def test_explosions_match_oracle(teno, oracle_mod, torch_cuda, key, order, variant, characteristic):
+    # the paper's explosion problems (Sec. 5.6) on the disc at h = 1/50
+    # (18,218 cells), transmissive rim: three RK steps against the oracle
+    torch = torch_cuda
+    w, m, U = inputs.make_workload(key)
+    print(f"[explosion] {w['name']} order={order} variant={variant} "
+          f"characteristic={characteristic} cells={m.n_cell}", flush=True)
+    kw = dict(order=order, fallback=1, variant=variant, characteristic=characteristic)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period).setup(**kw)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    om.setup(oracle_mod.params(**kw))
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    Ud = torch.as_tensor(U[perm], device="cuda")
+    Uo = U.copy()
+    for _ in range(3):
+        dto = om.dt(Uo, 0.4)
+        Uo = om.rk_step(Uo, dto)["U"]
+        sv.rk_step(Ud, torch.full((1,), dto, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    got = np.empty_like(Uo)
+    got[perm] = Ud.cpu().numpy()
+    _assert_states(got, Uo, f"{w['name']} after 3 steps")
+    assert not np.array_equal(Uo, U)

@@ -188,3 +188,25 @@ def test_box_setup_parity_with_oracle(teno, oracle_mod, order):
             a = lm.lsq_operator(i, k)
             b, _ = om.lsq_operator(i, k)
             assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
+
+
+def test_disc_setup_parity_with_oracle(teno, oracle_mod):
+    # the explosion problems' disc mesh: boundary faces, stencils and the
+    # least-squares operators agree with the oracle's
+    m = inputs.disc_mesh(1.0 / 14.0, 6)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    v, c = lm.boundary_faces()
+    v2, c2 = om.boundary_faces()
+    np.testing.assert_array_equal(v, v2)
+    np.testing.assert_array_equal(c, c2)
+    lm.setup(order=5)
+    om.setup(oracle_mod.params(order=5), all_cells=False)
+    for i in range(0, m.n_cell, 7):
+        for k in range(4):
+            np.testing.assert_array_equal(lm.stencil(i, k), om.stencil(i, k))
+    for i in (0, int(c[0]), m.n_cell - 1):
+        for k in range(4):
+            a = lm.lsq_operator(i, k)
+            b, _ = om.lsq_operator(i, k)
+            assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()

@@ -1099,3 +1099,43 @@ def test_boundary_face_flux_on_uniform_interior(oracle_mod, kind):
         assert np.abs(r).max() < 1e-12
     else:
         assert np.abs(expect).max() > 1e-3
+
+
+def test_disc_mesh_is_a_triangulation_of_the_inscribed_polygon(oracle_mod):
+    # the explosion problems' disc (Sec. 5.6): counter-clockwise cells that
+    # tile the polygon of the outer ring, whose vertices lie on the circle
+    m = inputs.disc_mesh(1.0 / 16.0, 3)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    area, cen, tri = om.geometry()
+    assert (area > 0).all()
+    verts, cells = om.boundary_faces()
+    r = np.hypot(*(m.xy[verts[:, 0]] - 1.0).T)
+    np.testing.assert_allclose(r, 1.0, rtol=0, atol=1e-14)
+    # the boundary faces close into one polygon; its shoelace area is the
+    # sum of the cell areas
+    assert sorted(verts[:, 0]) == sorted(verts[:, 1])
+    a, b = m.xy[verts[:, 0]] - 1.0, m.xy[verts[:, 1]] - 1.0
+    poly = 0.5 * (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]).sum()
+    assert area.sum() == pytest.approx(poly, rel=1e-13)
+    n_ring = round(2.0 * math.pi * 16.0)
+    assert len(verts) == n_ring
+    assert poly == pytest.approx(0.5 * n_ring * math.sin(2.0 * math.pi / n_ring), rel=1e-13)
+
+
+@pytest.mark.parametrize("which,order", [("ep01", 5), ("ep02", 3)])
+def test_explosion_conserves_while_the_rim_is_at_rest(oracle_mod, which, order):
+    # with the rim uniform and at rest, a transmissive face passes no mass or
+    # energy and its pressure forces cancel around the closed polygon, so all
+    # four totals are constant (to rounding) at the start of the explosions
+    m = inputs.disc_mesh(1.0 / 16.0, 5)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    om.setup(oracle_mod.params(order=order, fallback=1))
+    area, _, _ = om.geometry()
+    U = inputs.explosion(m, which)
+    inside = (U == inputs.conservative(*inputs.EXPLOSIONS[which][0])).all(1)
+    assert 0 < inside.sum() < len(U)
+    r = om.residual(U)
+    tot = (area[:, None] * r["R"]).sum(0)
+    scale = (area[:, None] * np.abs(r["R"])).sum(0)
+    assert (np.abs(tot) <= 1e-13 * scale.max()).all(), tot
+    assert scale[1] > 1e-3 and scale[3] > 1e-3          # the explosion has started
