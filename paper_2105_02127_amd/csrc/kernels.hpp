@@ -211,8 +211,14 @@ struct ReconArgs {
   int n_cell, n_tiles, n_pad;
   int frozen, variant, fallback, power;
   double ct, eps, gamma, tie_rel;
+  double tie_lo, tie_hi;               // near-tie window ct (1 -+ tie_rel); empty when ct = 0
   double cw_dK, cw_ds;                 // CWENO linear weights: large, each small
 };
+
+// chi within the near-tie window around C_T (counted, never decided on).
+__device__ __forceinline__ int near_tie(const ReconArgs& a, double chi) {
+  return (chi >= a.tie_lo && chi <= a.tie_hi) ? 1 : 0;
+}
 
 __device__ __forceinline__ double gamma_k(double beta, double eps, int power) {
   const double x = beta + eps;
@@ -426,12 +432,9 @@ __device__ __forceinline__ void small_part(const ReconArgs& a, bool frozen, unsi
     const double g1 = gamma_k(beta(1), a.eps, a.power);
     const double g2 = gamma_k(beta(2), a.eps, a.power);
     sp.ssum = (g0 + g1) + g2;
-    const double x0 = g0 / sp.ssum, x1 = g1 / sp.ssum, x2 = g2 / sp.ssum;
-    if (a.ct > 0.0) {
-      sp.ties += fabs(x0 / a.ct - 1.0) <= a.tie_rel;
-      sp.ties += fabs(x1 / a.ct - 1.0) <= a.tie_rel;
-      sp.ties += fabs(x2 / a.ct - 1.0) <= a.tie_rel;
-    }
+    const double is = 1.0 / sp.ssum;
+    const double x0 = g0 * is, x1 = g1 * is, x2 = g2 * is;
+    sp.ties += near_tie(a, x0) + near_tie(a, x1) + near_tie(a, x2);
     sp.nsm = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
   }
   if constexpr (!CW) {
@@ -490,7 +493,7 @@ __device__ __forceinline__ void large_part(const ReconArgs& a, bool frozen, unsi
     } else if (a.variant == 0) {
       const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
       const double chiK = gK / (sp.ssum + gK);
-      if (a.ct > 0.0 && fabs(chiK / a.ct - 1.0) <= a.tie_rel) ++ties;
+      ties += near_tie(a, chiK);
       keepK = chiK >= a.ct;
       if (!keepK) ties += sp.ties;
     }
@@ -525,6 +528,29 @@ __device__ __forceinline__ CharState char_state(double u0, double g) {
   S.ic = 1.0 / S.c;
   S.H = (en + p) * ir;
   S.b1 = (g - 1.0) * S.ic * S.ic;
+  S.b2 = 0.5 * S.q2 * S.b1;
+  return S;
+}
+
+// The part of the state that costs a division or a square root (u = m / rho,
+// c, 1 / c), kept across a cell's edges where registers allow; the rest is
+// formed again from it on each edge, with H = c^2 / (gamma - 1) + |u|^2 / 2.
+struct CharCore {
+  double ux, uy, c, ic;
+};
+__device__ __forceinline__ CharCore char_core(const CharState& S) { return {S.ux, S.uy, S.c, S.ic}; }
+__device__ __forceinline__ CharState char_expand(CharCore K, double g) {
+  // opaque copies: left visible, the expansion is the same on every edge
+  // and the compiler forms it once and holds all of it
+  asm volatile("" : "+v"(K.ux), "+v"(K.uy), "+v"(K.c), "+v"(K.ic));
+  CharState S;
+  S.ux = K.ux;
+  S.uy = K.uy;
+  S.q2 = K.ux * K.ux + K.uy * K.uy;
+  S.c = K.c;
+  S.ic = K.ic;
+  S.H = K.c * K.c / (g - 1.0) + 0.5 * S.q2;
+  S.b1 = (g - 1.0) * K.ic * K.ic;
   S.b2 = 0.5 * S.q2 * S.b1;
   return S;
 }
@@ -598,6 +624,11 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
   const int side = a.nbinfo[live ? cell : 0].w;  // face normals point out of the L side
   int ties = 0;
   bool fp_ok = true;
+  // TENO keeps the costly part of the projection state across the edges;
+  // CWENO, with more registers live, forms it again on each edge
+  constexpr bool keep_core = !CW;
+  const CharCore core = keep_core ? char_core(char_state(u0, a.gamma)) : CharCore{};
+  auto state = [&]() { return keep_core ? char_expand(core, a.gamma) : char_state(u0, a.gamma); };
   static_for<0, 3>([&](auto E) {
     constexpr int e = E;
     // one edge at a time: keeps the scheduler from overlapping the edges
@@ -609,7 +640,7 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
     SmallPart<CW> sp;
     {
       double lrow[4];
-      char_lrow(char_state(u0, a.gamma), nx, ny, avg_ok, v, lrow);
+      char_lrow(state(), nx, ny, avg_ok, v, lrow);
 #pragma unroll
       for (int l = 0; l < NU; ++l) wK[l] = quad_dot(lrow, aK[l]);
       // The small stencils' projected coefficients are held for the
@@ -634,7 +665,7 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
     unsigned nib = 0u;
     large_part<P, CW>(a, false, 8u, sp, wK, ab, nib, ties);
     double rrow[4];
-    char_rrow(char_state(u0, a.gamma), nx, ny, avg_ok, v, rrow);
+    char_rrow(state(), nx, ny, avg_ok, v, rrow);
     const double* __restrict__ fb = &FaceBasis<O::R, NQ>::P.v[e * NQ][0];
 #pragma unroll
     for (int kq = 0; kq < NQ; ++kq) {

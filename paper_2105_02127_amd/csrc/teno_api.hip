@@ -165,6 +165,18 @@ int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
 }
 
 // Doubles of one stage's face states in the library layout [3 nq][n_pad][4].
+// chi counts as a near tie when |chi / C_T - 1| <= tie_rel; an empty window
+// when C_T = 0 (the linear scheme has no ties).
+static void set_tie_window(ReconArgs& a) {
+  if (a.ct > 0.0) {
+    a.tie_lo = a.ct * (1.0 - a.tie_rel);
+    a.tie_hi = a.ct * (1.0 + a.tie_rel);
+  } else {
+    a.tie_lo = 1.0;
+    a.tie_hi = 0.0;
+  }
+}
+
 static size_t face_state_doubles(const teno_solver* s) { return (size_t)3 * s->d.nq * s->n_pad * 4; }
 
 // fp: face-state buffer of the launch (library layout), nullptr = the
@@ -195,6 +207,7 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   a.eps = s->prm.eps;
   a.gamma = s->prm.gamma;
   a.tie_rel = s->prm.tie_rel;
+  set_tie_window(a);
   a.cw_dK = 1.0 - 1.0 / s->prm.dk_prime;
   a.cw_ds = (1.0 - a.cw_dK) / 3.0;
   const int blocks = (s->n_tiles + 3) / 4;
@@ -1032,6 +1045,7 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
       a.eps = s->prm.eps;
       a.gamma = s->prm.gamma;
       a.tie_rel = s->prm.tie_rel;
+      set_tie_window(a);
       CellUpdateArgs& c = d.cu[k];
       c.cfaces = s->cfaces;
       c.vol = s->vol;
