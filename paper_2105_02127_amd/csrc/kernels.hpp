@@ -240,6 +240,32 @@ __device__ __forceinline__ double quad_form(const double (&B)[N][N], const doubl
   return s;
 }
 
+// The same form from U, the upper triangle of B with its off-diagonal
+// entries doubled: about half the multiply-adds, but with fewer
+// instructions between them the compiler keeps more values live.
+template <int N>
+__device__ __forceinline__ double quad_form_upper(const double (&U)[N][N], const double* a) {
+  double s = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    double t = U[l][l] * a[l];
+#pragma unroll
+    for (int m = l + 1; m < N; ++m) t = fma(U[l][m], a[m], t);
+    s = fma(a[l], t, s);
+  }
+  return s;
+}
+
+// beta = a^T B a of degree R from the full table, or from its doubled upper
+// triangle (UP).
+template <int R, bool UP>
+__device__ __forceinline__ double smoothness(const double* a) {
+  if constexpr (UP)
+    return quad_form_upper(SmoothForm<R>::U.v, a);
+  else
+    return quad_form(SmoothForm<R>::B.v, a);
+}
+
 // Broadcast lane K of every group of four lanes (DPP quad permutation).
 template <int K>
 __device__ __forceinline__ double quad_bcast(double x) {
@@ -417,14 +443,14 @@ struct SmallPart {
 // the indicators and for the combination (a caller may recompute it rather
 // than hold all fifteen values).  Both are called by all lanes of a cell
 // together, never under a lane-dependent condition.
-template <bool CW, class BCoef, class CCoef>
+template <bool CW, bool UP = false, class BCoef, class CCoef>
 __device__ __forceinline__ void small_part(const ReconArgs& a, bool frozen, unsigned nib_in,
                                            BCoef&& bcoef, CCoef&& coef, SmallPart<CW>& sp) {
   auto beta = [&](int k) {
     double w[5];
 #pragma unroll
     for (int l = 0; l < 5; ++l) w[l] = bcoef(k, l);
-    return quad_form(SmoothForm<2>::B.v, w);
+    return smoothness<2, UP>(w);
   };
   sp.nsm = nib_in & 7u;
   if (!CW && !frozen && a.variant == 0) {
@@ -471,7 +497,7 @@ __device__ __forceinline__ void small_part(const ReconArgs& a, bool frozen, unsi
 // Large part: TENO step one (Sec. 3.2) and the selected coefficients, or
 // the CWENO combination P = (w_K/d_K)(P_K - sum_k d_k P_k) + sum_k w_k P_k.
 // ab gets the combined coefficients, nib the variable's 4-bit flag.
-template <int P, bool CW>
+template <int P, bool CW, bool UP = false>
 __device__ __forceinline__ void large_part(const ReconArgs& a, bool frozen, unsigned nib_in,
                                            const SmallPart<CW>& sp,
                                            const double (&aK)[OrderT<P>::NU],
@@ -479,7 +505,7 @@ __device__ __forceinline__ void large_part(const ReconArgs& a, bool frozen, unsi
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   if constexpr (CW) {
-    const double wK = a.cw_dK * gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
+    const double wK = a.cw_dK * gamma_k(smoothness<O::R, UP>(aK), a.eps, a.power);
     const double iS = 1.0 / (sp.ssum + wK);
     const double cK = wK / a.cw_dK;
 #pragma unroll
@@ -491,7 +517,7 @@ __device__ __forceinline__ void large_part(const ReconArgs& a, bool frozen, unsi
     if (frozen) {
       keepK = (nib_in & 8u) != 0;
     } else if (a.variant == 0) {
-      const double gK = gamma_k(quad_form(SmoothForm<O::R>::B.v, aK), a.eps, a.power);
+      const double gK = gamma_k(smoothness<O::R, UP>(aK), a.eps, a.power);
       const double chiK = gK / (sp.ssum + gK);
       ties += near_tie(a, chiK);
       keepK = chiK >= a.ct;
@@ -627,6 +653,10 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
   // TENO keeps the costly part of the projection state across the edges;
   // CWENO, with more registers live, forms it again on each edge
   constexpr bool keep_core = !CW;
+  // the indicators from the doubled upper triangles (half the multiply-adds)
+  // where that keeps the kernel's waves per SIMD: TENO up to order 5; at
+  // order 6 and for CWENO it costs a wave and measured 6-9% slower
+  constexpr bool kUpper = !CW && P <= 5;
   const CharCore core = keep_core ? char_core(char_state(u0, a.gamma)) : CharCore{};
   auto state = [&]() { return keep_core ? char_expand(core, a.gamma) : char_state(u0, a.gamma); };
   static_for<0, 3>([&](auto E) {
@@ -651,7 +681,7 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
       constexpr bool hold = CW || P == 3 || P == 5;
       if constexpr (!hold) {
         auto proj = [&](int k, int l) { return quad_dot(lrow, as[k][l]); };
-        small_part<CW>(a, false, 8u, proj, proj, sp);
+        small_part<CW, kUpper>(a, false, 8u, proj, proj, sp);
       } else {
         double ws[3][5];
 #pragma unroll
@@ -659,11 +689,11 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
 #pragma unroll
           for (int l = 0; l < 5; ++l) ws[k][l] = quad_dot(lrow, as[k][l]);
         auto held = [&](int k, int l) { return ws[k][l]; };
-        small_part<CW>(a, false, 8u, held, held, sp);
+        small_part<CW, kUpper>(a, false, 8u, held, held, sp);
       }
     }
     unsigned nib = 0u;
-    large_part<P, CW>(a, false, 8u, sp, wK, ab, nib, ties);
+    large_part<P, CW, kUpper>(a, false, 8u, sp, wK, ab, nib, ties);
     double rrow[4];
     char_rrow(state(), nx, ny, avg_ok, v, rrow);
     const double* __restrict__ fb = &FaceBasis<O::R, NQ>::P.v[e * NQ][0];
@@ -1328,6 +1358,27 @@ __global__ __launch_bounds__(256) void k_batch_reconstruct(const BatchMeshDev* _
     const BatchMeshDev& d = meshes[m];
     batch_tile<PQ>(d.pq, d.r[stage_k], tile, lane, lds + wave * lds_stride);
   }
+}
+
+// The same with one (mesh, tile) item per wavefront and no loop.  In the
+// persistent form the compiler hoists the constant tables' addresses out of
+// the item loop and holds them, spilling scalar registers into vector ones
+// (141 VGPRs at order 5 against 104 for one mesh); without the loop it keeps
+// the single-mesh kernel's budget.
+template <int PQ>
+__global__ __launch_bounds__(256) void k_batch_reconstruct_one(const BatchMeshDev* __restrict__ meshes,
+                                                               const int2* __restrict__ items,
+                                                               int n_items, int stage_k,
+                                                               int lds_stride) {
+  extern __shared__ int4 lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (w >= n_items) return;
+  const int2 it = items[w];
+  const int m = __builtin_amdgcn_readfirstlane(it.x);
+  const int tile = __builtin_amdgcn_readfirstlane(it.y);
+  const BatchMeshDev& d = meshes[m];
+  batch_tile<PQ>(d.pq, d.r[stage_k], tile, lane, lds + wave * lds_stride);
 }
 
 // Persistent face fluxes over (mesh, 64-face chunk) items.

@@ -79,6 +79,15 @@ struct SmoothForm {
     return M;
   }
   static constexpr Mat B = make();
+  // upper triangle of B with the off-diagonal entries doubled:
+  // a^T B a = sum_l a_l (U_ll a_l + sum_{m>l} U_lm a_m)
+  static constexpr Mat upper() {
+    Mat M{};
+    for (int l = 0; l < N; ++l)
+      for (int m = l; m < N; ++m) M.v[l][m] = (m == l ? 1.0 : 2.0) * B.v[l][m];
+    return M;
+  }
+  static constexpr Mat U = upper();
 };
 
 // Gauss-Legendre points on [0,1] (t) and weights summing to one (w).

@@ -1088,11 +1088,18 @@ void batch_launch_recon(teno_batch* b, int k, hipStream_t st) {
     const int blocks = (L.n_waves + 3) / 4;
     const int* ws = b->start_r + L.wave0;
     const size_t lds = (size_t)4 * L.lds_stride * sizeof(int4);
+    // one wavefront per item: the loop-free kernel over this launch's items
+    const bool one = b->tune.waves_per_cu == 0;
+    const int2* its = b->items_r + L.item0;
     switch (L.pq) {
 #define TENO_BATCH_CASE(PQ)                                                                  \
   case PQ:                                                                                   \
-    hipLaunchKernelGGL((k_batch_reconstruct<PQ>), dim3(blocks), dim3(256), lds, st,          \
-                       b->meshes, b->items_r, ws, L.n_waves, k, L.lds_stride);               \
+    if (one)                                                                                 \
+      hipLaunchKernelGGL((k_batch_reconstruct_one<PQ>), dim3(blocks), dim3(256), lds, st,    \
+                         b->meshes, its, L.n_waves, k, L.lds_stride);                        \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_batch_reconstruct<PQ>), dim3(blocks), dim3(256), lds, st,        \
+                         b->meshes, b->items_r, ws, L.n_waves, k, L.lds_stride);             \
     break;
       TENO_BATCH_CASE(0)
       TENO_BATCH_CASE(32)
