@@ -61,128 +61,43 @@ __device__ __forceinline__ bool physical(double r, double mx, double my, double 
   return p > 0.0;
 }
 
-// Forward-mode dual number with NDIR directional derivatives (adjoint only).
-template <int NDIR>
-struct Dual {
-  double v;
-  double d[NDIR];
-};
-
-template <int N>
-__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r;
-  r.v = a.v + b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r;
-  r.v = a.v - b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r;
-  r.v = a.v * b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r;
-  r.v = a.v / b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator*(double s, const Dual<N>& a) {
-  Dual<N> r;
-  r.v = s * a.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator+(double s, const Dual<N>& a) {
-  Dual<N> r = a;
-  r.v = s + a.v;
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a) {
-  Dual<N> r;
-  r.v = -a.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
-  return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> dsqrt(const Dual<N>& a) {
-  Dual<N> r;
-  r.v = sqrt(a.v);
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / (2.0 * r.v);
-  return r;
-}
-__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
-__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
-template <int N>
-__device__ __forceinline__ Dual<N> recip(const Dual<N>& a) {
-  Dual<N> r;
-  r.v = 1.0 / a.v;
-  const double r2 = r.v * r.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i] * r2;
-  return r;
-}
-template <int N>
-__device__ __forceinline__ double vof(const Dual<N>& a) { return a.v; }
-__device__ __forceinline__ double vof(double a) { return a; }
-
 // HLL flux through unit normal (nx, ny): rotate into the face frame, HLL with
 // S_L = min(u_L - c_L, u~ - c~), S_R = max(u_R + c_R, u~ + c~) from Roe
 // averages (both velocity components in c~), rotate back.  The quotients
 // share four reciprocals (1/rho_L, 1/rho_R, 1/(1 + sqrt(rho_R/rho_L)),
 // 1/(S_R - S_L)): FP64 division is a long instruction sequence and this
 // function is most of the flux kernel's work.
-template <class T>
-__device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, double ny, double g,
-                                    T out[4]) {
-  const T L0 = uL[0], L1 = nx * uL[1] + ny * uL[2], L2 = nx * uL[2] + (-ny) * uL[1], L3 = uL[3];
-  const T R0 = uR[0], R1 = nx * uR[1] + ny * uR[2], R2 = nx * uR[2] + (-ny) * uR[1], R3 = uR[3];
-  const T iL = recip(L0), iR = recip(R0);
-  const T unL = L1 * iL, utL = L2 * iL, unR = R1 * iR, utR = R2 * iR;
-  const T pL = (g - 1.0) * (L3 - (0.5 * L0) * (unL * unL + utL * utL));
-  const T pR = (g - 1.0) * (R3 - (0.5 * R0) * (unR * unR + utR * utR));
-  const T cL = dsqrt(g * pL * iL), cR = dsqrt(g * pR * iR);
-  const T HL = (L3 + pL) * iL, HR = (R3 + pR) * iR;
-  const T D = dsqrt(R0 * iL);
-  const T iden = recip(1.0 + D);
-  const T ut = (unL + D * unR) * iden, vt = (utL + D * utR) * iden, Ht = (HL + D * HR) * iden;
-  const T ct = dsqrt((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)));
-  const T a1 = unL - cL, a2 = ut - ct;
-  const T SL = vof(a2) < vof(a1) ? a2 : a1;
-  const T b1 = unR + cR, b2 = ut + ct;
-  const T SR = vof(b2) > vof(b1) ? b2 : b1;
-  const T FL[4] = {L1, L1 * unL + pL, L1 * utL, unL * (L3 + pL)};
-  const T FR[4] = {R1, R1 * unR + pR, R1 * utR, unR * (R3 + pR)};
-  const T UL[4] = {L0, L1, L2, L3};
-  const T UR[4] = {R0, R1, R2, R3};
-  T F[4];
-  if (vof(SL) >= 0.0) {
+__device__ __forceinline__ void hll(const double uL[4], const double uR[4], double nx, double ny,
+                                    double g, double out[4]) {
+  const double L0 = uL[0], L1 = nx * uL[1] + ny * uL[2], L2 = nx * uL[2] + (-ny) * uL[1], L3 = uL[3];
+  const double R0 = uR[0], R1 = nx * uR[1] + ny * uR[2], R2 = nx * uR[2] + (-ny) * uR[1], R3 = uR[3];
+  const double iL = 1.0 / L0, iR = 1.0 / R0;
+  const double unL = L1 * iL, utL = L2 * iL, unR = R1 * iR, utR = R2 * iR;
+  const double pL = (g - 1.0) * (L3 - (0.5 * L0) * (unL * unL + utL * utL));
+  const double pR = (g - 1.0) * (R3 - (0.5 * R0) * (unR * unR + utR * utR));
+  const double cL = sqrt(g * pL * iL), cR = sqrt(g * pR * iR);
+  const double HL = (L3 + pL) * iL, HR = (R3 + pR) * iR;
+  const double D = sqrt(R0 * iL);
+  const double iden = 1.0 / (1.0 + D);
+  const double ut = (unL + D * unR) * iden, vt = (utL + D * utR) * iden, Ht = (HL + D * HR) * iden;
+  const double ct = sqrt((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)));
+  const double a1 = unL - cL, a2 = ut - ct;
+  const double SL = a2 < a1 ? a2 : a1;
+  const double b1 = unR + cR, b2 = ut + ct;
+  const double SR = b2 > b1 ? b2 : b1;
+  const double FL[4] = {L1, L1 * unL + pL, L1 * utL, unL * (L3 + pL)};
+  const double FR[4] = {R1, R1 * unR + pR, R1 * utR, unR * (R3 + pR)};
+  const double UL[4] = {L0, L1, L2, L3};
+  const double UR[4] = {R0, R1, R2, R3};
+  double F[4];
+  if (SL >= 0.0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[c] = FL[c];
-  } else if (vof(SR) <= 0.0) {
+  } else if (SR <= 0.0) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[c] = FR[c];
   } else {
-    const T iS = recip(SR - SL);
+    const double iS = 1.0 / (SR - SL);
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[c] = (SR * FL[c] - SL * FR[c] + SL * SR * (UR[c] - UL[c])) * iS;
   }
@@ -190,6 +105,149 @@ __device__ __forceinline__ void hll(const T uL[4], const T uR[4], double nx, dou
   out[1] = nx * F[1] - ny * F[2];
   out[2] = ny * F[1] + nx * F[2];
   out[3] = F[3];
+}
+
+// Reverse mode of hll (the same flux, the same branches): adds
+// ob^T d(out)/d(uL) to gL and ob^T d(out)/d(uR) to gR.  The speed selections
+// and the flux case follow the primal values, as the flux does.  One pass
+// forward, one back: both sides' adjoints for about three times the flux's
+// arithmetic.
+__device__ __forceinline__ void hll_vjp(const double uL[4], const double uR[4], double nx,
+                                        double ny, double g, const double ob[4], double gL[4],
+                                        double gR[4]) {
+  const double gm = g - 1.0;
+  // ---- primal, keeping what the reverse pass needs ----
+  const double L0 = uL[0], L1 = nx * uL[1] + ny * uL[2], L2 = nx * uL[2] + (-ny) * uL[1], L3 = uL[3];
+  const double R0 = uR[0], R1 = nx * uR[1] + ny * uR[2], R2 = nx * uR[2] + (-ny) * uR[1], R3 = uR[3];
+  const double iL = 1.0 / L0, iR = 1.0 / R0;
+  const double unL = L1 * iL, utL = L2 * iL, unR = R1 * iR, utR = R2 * iR;
+  const double qL = unL * unL + utL * utL, qR = unR * unR + utR * utR;
+  const double pL = gm * (L3 - (0.5 * L0) * qL), pR = gm * (R3 - (0.5 * R0) * qR);
+  const double cL = sqrt(g * pL * iL), cR = sqrt(g * pR * iR);
+  const double EL = L3 + pL, ER = R3 + pR;  // rho H
+  const double HL = EL * iL, HR = ER * iR;
+  const double D = sqrt(R0 * iL);
+  const double iden = 1.0 / (1.0 + D);
+  const double nu = unL + D * unR, nv = utL + D * utR, nH = HL + D * HR;
+  const double ut = nu * iden, vt = nv * iden, Ht = nH * iden;
+  const double ct = sqrt(gm * (Ht - 0.5 * (ut * ut + vt * vt)));
+  const double a1 = unL - cL, a2 = ut - ct;
+  const bool l2 = a2 < a1;
+  const double SL = l2 ? a2 : a1;
+  const double b1 = unR + cR, b2 = ut + ct;
+  const bool r2 = b2 > b1;
+  const double SR = r2 ? b2 : b1;
+  const double FL[4] = {L1, L1 * unL + pL, L1 * utL, unL * EL};
+  const double FR[4] = {R1, R1 * unR + pR, R1 * utR, unR * ER};
+  const double UL[4] = {L0, L1, L2, L3}, UR[4] = {R0, R1, R2, R3};
+  // ---- reverse ----
+  // out = (F0, nx F1 - ny F2, ny F1 + nx F2, F3)
+  const double Fb[4] = {ob[0], nx * ob[1] + ny * ob[2], nx * ob[2] - ny * ob[1], ob[3]};
+  double FLb[4] = {0.0, 0.0, 0.0, 0.0}, FRb[4] = {0.0, 0.0, 0.0, 0.0};
+  double Lb[4] = {0.0, 0.0, 0.0, 0.0}, Rb[4] = {0.0, 0.0, 0.0, 0.0};
+  double SLb = 0.0, SRb = 0.0;
+  if (SL >= 0.0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) FLb[c] = Fb[c];
+  } else if (SR <= 0.0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) FRb[c] = Fb[c];
+  } else {
+    // F_c = N_c iS, N_c = SR FL_c - SL FR_c + SL SR (UR_c - UL_c), iS = 1 / (SR - SL)
+    const double iS = 1.0 / (SR - SL);
+    double iSb = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double dU = UR[c] - UL[c];
+      const double N = SR * FL[c] - SL * FR[c] + SL * SR * dU;
+      const double Nb = Fb[c] * iS;
+      iSb += Fb[c] * N;
+      FLb[c] = SR * Nb;
+      FRb[c] = -SL * Nb;
+      SRb += Nb * (FL[c] + SL * dU);
+      SLb += Nb * (SR * dU - FR[c]);
+      Rb[c] += SL * SR * Nb;
+      Lb[c] -= SL * SR * Nb;
+    }
+    const double t = -iS * iS * iSb;  // d(iS) = -iS^2 d(SR - SL)
+    SRb += t;
+    SLb -= t;
+  }
+  // the physical fluxes
+  Lb[1] += FLb[0] + FLb[1] * unL + FLb[2] * utL;
+  Rb[1] += FRb[0] + FRb[1] * unR + FRb[2] * utR;
+  double unLb = FLb[1] * L1 + FLb[3] * EL, unRb = FRb[1] * R1 + FRb[3] * ER;
+  double utLb = FLb[2] * L1, utRb = FRb[2] * R1;
+  double pLb = FLb[1], pRb = FRb[1];
+  double ELb = FLb[3] * unL, ERb = FRb[3] * unR;
+  // the wave-speed estimates
+  const double a1b = l2 ? 0.0 : SLb, a2b = l2 ? SLb : 0.0;
+  const double b1b = r2 ? 0.0 : SRb, b2b = r2 ? SRb : 0.0;
+  unLb += a1b;
+  const double cLb = -a1b;
+  unRb += b1b;
+  const double cRb = b1b;
+  double utb = a2b + b2b;
+  const double ctb = b2b - a2b;
+  // ct = sqrt(X), X = (g - 1) (Ht - (ut^2 + vt^2) / 2)
+  const double Xb = ctb * 0.5 / ct;
+  const double Htb = gm * Xb;
+  utb -= gm * ut * Xb;
+  const double vtb = -gm * vt * Xb;
+  // Roe averages: ut = nu iden, vt = nv iden, Ht = nH iden
+  const double nub = utb * iden, nvb = vtb * iden, nHb = Htb * iden;
+  const double idenb = utb * nu + vtb * nv + Htb * nH;
+  unLb += nub;
+  unRb += D * nub;
+  utLb += nvb;
+  utRb += D * nvb;
+  const double HLb = nHb, HRb = D * nHb;
+  double Db = unR * nub + utR * nvb + HR * nHb - iden * iden * idenb;
+  // D = sqrt(R0 iL)
+  const double Yb = Db * 0.5 / D;
+  Rb[0] += Yb * iL;
+  double iLb = Yb * R0, iRb = 0.0;
+  // H = (E + p) / rho
+  ELb += HLb * iL;
+  iLb += HLb * EL;
+  ERb += HRb * iR;
+  iRb += HRb * ER;
+  // c = sqrt(g p / rho)
+  const double ZLb = cLb * 0.5 / cL, ZRb = cRb * 0.5 / cR;
+  pLb += g * iL * ZLb + ELb;
+  iLb += g * pL * ZLb;
+  pRb += g * iR * ZRb + ERb;
+  iRb += g * pR * ZRb;
+  Lb[3] += ELb;
+  Rb[3] += ERb;
+  // p = (g - 1) (E - rho q / 2)
+  Lb[3] += gm * pLb;
+  Rb[3] += gm * pRb;
+  Lb[0] -= 0.5 * gm * qL * pLb;
+  Rb[0] -= 0.5 * gm * qR * pRb;
+  const double qLb = -0.5 * gm * L0 * pLb, qRb = -0.5 * gm * R0 * pRb;
+  unLb += 2.0 * unL * qLb;
+  utLb += 2.0 * utL * qLb;
+  unRb += 2.0 * unR * qRb;
+  utRb += 2.0 * utR * qRb;
+  // un = m_n / rho, ut = m_t / rho
+  Lb[1] += unLb * iL;
+  Lb[2] += utLb * iL;
+  iLb += unLb * L1 + utLb * L2;
+  Rb[1] += unRb * iR;
+  Rb[2] += utRb * iR;
+  iRb += unRb * R1 + utRb * R2;
+  Lb[0] -= iL * iL * iLb;
+  Rb[0] -= iR * iR * iRb;
+  // the rotation into the face frame
+  gL[0] += Lb[0];
+  gL[1] += nx * Lb[1] - ny * Lb[2];
+  gL[2] += ny * Lb[1] + nx * Lb[2];
+  gL[3] += Lb[3];
+  gR[0] += Rb[0];
+  gR[1] += nx * Rb[1] - ny * Rb[2];
+  gR[2] += ny * Rb[1] + nx * Rb[2];
+  gR[3] += Rb[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -957,7 +1015,7 @@ __device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f, int b = 
       uR[3] = r1.y;
     }
     double F[4];
-    hll<double>(uL, uR, nrm.x, nrm.y, a.gamma, F);
+    hll(uL, uR, nrm.x, nrm.y, a.gamma, F);
 #pragma unroll
     for (int c = 0; c < 4; ++c) phi[c] = phi[c] + FaceRule<NQ>::w[k] * F[c];
   }
@@ -1088,14 +1146,10 @@ __global__ __launch_bounds__(256) void k_dt_final(const double* __restrict__ par
 // ---------------------------------------------------------------------------
 // adjoint of the residual (selection frozen)
 // ---------------------------------------------------------------------------
-// Phase 1 (one lane per (face, side)): adjoint of the face-point states.
-// Face f gets Phi_bar = lam_R/|V_R| - lam_L/|V_L| (scaled by `scale`); the
-// lane takes the HLL Jacobian of its face with respect to the state of one
-// side only (dual numbers seeded on that argument at compile time) and
-// writes that side's face-point adjoints.  Blocks hold one side each, so no
-// wavefront mixes the two seedings (a per-cell loop over its edges mixes L
-// and R sides in a wavefront and evaluates the dual HLL under both
-// branches).
+// Phase 1 (one lane per face): adjoint of the face-point states.  Face f
+// gets Phi_bar = lam_R/|V_R| - lam_L/|V_L| (scaled by `scale`); at each of
+// its Gauss points the lane runs the reverse mode of the HLL flux (hll_vjp)
+// and writes both sides' face-point adjoints.
 struct AdjFaceArgs {
   const double* __restrict__ fp;      // [3 nq][n_pad][4]
   const int4* __restrict__ fcell;     // [n_face]: L, R, eL | eR << 2
@@ -1109,8 +1163,8 @@ struct AdjFaceArgs {
   int n_face, n_pad;
 };
 
-template <int NQ, int SIDE>
-__device__ __forceinline__ void adj_face_side(const AdjFaceArgs& a, int f) {
+template <int NQ>
+__device__ __forceinline__ void adj_face(const AdjFaceArgs& a, int f) {
   const int4 fc = a.fcell[f];
   const double2 nrm = a.fgeo[2 * (size_t)f], len = a.fgeo[2 * (size_t)f + 1];
   const int L = fc.x, R = fc.y, eL = fc.z & 3, eR = (fc.z >> 2) & 3;
@@ -1121,51 +1175,28 @@ __device__ __forceinline__ void adj_face_side(const AdjFaceArgs& a, int f) {
   for (int c = 0; c < 4; ++c)
     pb[c] = sc * (a.lam[(size_t)R * 4 + c] / aR - a.lam[(size_t)L * 4 + c] / aL);
   const double2* fp2 = reinterpret_cast<const double2*>(a.fp);
+  double2* out2 = reinterpret_cast<double2*>(a.fpbar);
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int qL = eL * NQ + k, qR = eR * NQ + NQ - 1 - k;
     const size_t oL = ((size_t)qL * a.n_pad + L) * 2, oR = ((size_t)qR * a.n_pad + R) * 2;
     const double2 l0 = fp2[oL], l1 = fp2[oL + 1], r0 = fp2[oR], r1 = fp2[oR + 1];
     const double vl[4] = {l0.x, l0.y, l1.x, l1.y}, vr[4] = {r0.x, r0.y, r1.x, r1.y};
-    Dual<4> uL[4], uR[4], F[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      uL[c].v = vl[c];
-      uR[c].v = vr[c];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        uL[c].d[d] = (SIDE == 0 && c == d) ? 1.0 : 0.0;
-        uR[c].d[d] = (SIDE == 1 && c == d) ? 1.0 : 0.0;
-      }
-    }
-    hll<Dual<4>>(uL, uR, nrm.x, nrm.y, a.gamma, F);
+    double gL[4] = {0.0, 0.0, 0.0, 0.0}, gR[4] = {0.0, 0.0, 0.0, 0.0};
+    hll_vjp(vl, vr, nrm.x, nrm.y, a.gamma, pb, gL, gR);
     const double w = len.x * FaceRule<NQ>::w[k];
-    const int q = SIDE == 0 ? qL : qR, cell = SIDE == 0 ? L : R;
-    double* out = a.fpbar + ((size_t)q * a.n_pad + cell) * 4;
-    double o[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) s = fma(pb[c], F[c].d[d], s);
-      o[d] = w * s;
-    }
-    reinterpret_cast<double2*>(out)[0] = make_double2(o[0], o[1]);
-    reinterpret_cast<double2*>(out)[1] = make_double2(o[2], o[3]);
+    out2[oL] = make_double2(w * gL[0], w * gL[1]);
+    out2[oL + 1] = make_double2(w * gL[2], w * gL[3]);
+    out2[oR] = make_double2(w * gR[0], w * gR[1]);
+    out2[oR + 1] = make_double2(w * gR[2], w * gR[3]);
   }
 }
 
-// Grid: 2 * nfb blocks, the first nfb for the L sides, the rest for the R sides.
 template <int NQ>
-__global__ __launch_bounds__(256) void k_adj_face_sides(AdjFaceArgs a, int nfb) {
-  const int side = blockIdx.x >= (unsigned)nfb;
-  const int b = blockIdx.x - side * nfb;
-  const int f = xcd_remap(b, nfb) * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_adj_faces(AdjFaceArgs a) {
+  const int f = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (f >= a.n_face) return;
-  if (side == 0)
-    adj_face_side<NQ, 0>(a, f);
-  else
-    adj_face_side<NQ, 1>(a, f);
+  adj_face<NQ>(a, f);
 }
 
 // Phase 2 (one wavefront per tile, one lane per (cell, variable)):

@@ -322,8 +322,7 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   const int qblocks = (int)(((int64_t)s->n_cell * 4 + 255) / 256);
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 3, st, [&]() {
-      hipLaunchKernelGGL((k_adj_face_sides<decltype(NQ)::value>), dim3(2 * fblocks), dim3(256), 0,
-                         st, ff, fblocks);
+      hipLaunchKernelGGL((k_adj_faces<decltype(NQ)::value>), dim3(fblocks), dim3(256), 0, st, ff);
       hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
                          dim3(256), (size_t)4 * s->ustride * 4 * sizeof(double), st, ra);
       hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->tbar,
