@@ -4,8 +4,8 @@ The stencil selection of every stage and the step sizes are frozen at the
 values of the forward pass.  For fixed selection the reconstruction is linear
 in the cell averages, so the step map is differentiable wherever the HLL flux
 is, and its vector-Jacobian product is what `teno_vjp_rk_step` computes on the
-device (HLL Jacobian by forward-mode dual numbers, reconstruction transposed
-by a reverse-stencil gather, no atomics).
+device (the HLL flux differentiated in reverse mode, the reconstruction
+transposed into per-tile sums and a reverse-stencil gather, no atomics).
 
 Memory: U is checkpointed every `checkpoint_every` steps; the backward pass
 recomputes one segment at a time (its stage states, flags and, unless
