@@ -210,3 +210,23 @@ def test_disc_setup_parity_with_oracle(teno, oracle_mod):
             a = lm.lsq_operator(i, k)
             b, _ = om.lsq_operator(i, k)
             assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
+
+
+def test_degenerate_meshes_are_refused(teno, oracle_mod):
+    # empty input, out-of-range vertex ids, and meshes with too few cells for
+    # the stencils: both sides refuse with a message, neither crashes
+    tri1 = np.array([[0, 1, 2]], np.int32)
+    xy3 = np.array([[0.0, 0.0], [0.5, 0.0], [0.0, 0.5]])
+    with pytest.raises(teno.TenoError, match="empty"):
+        teno.Mesh(np.zeros((0, 2)), np.zeros((0, 3), np.int32))
+    with pytest.raises(RuntimeError, match="empty"):
+        oracle_mod.OracleMesh(np.zeros((0, 2)), np.zeros((0, 3), np.int32))
+    with pytest.raises(teno.TenoError, match="out of range"):
+        teno.Mesh(xy3, np.array([[0, 1, 5]], np.int32), period=(0.0, 0.0))
+    with pytest.raises(teno.TenoError, match="too few"):
+        teno.Mesh(xy3, tri1, period=(0.0, 0.0)).setup(order=3)
+    box = inputs.jittered_box_mesh(3, 3, 1)
+    with pytest.raises(teno.TenoError, match="too few"):
+        teno.Mesh(box.xy, box.tri, period=box.period).setup(order=6)
+    with pytest.raises(RuntimeError, match="too few"):
+        oracle_mod.OracleMesh(box.xy, box.tri, period=box.period).setup(oracle_mod.params(order=6))
