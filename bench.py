@@ -68,6 +68,30 @@ def traffic_from_profiles(workload: str):
         return None
 
 
+def stream_triad_gbs(torch, n=1 << 26, reps=20):
+    """Achievable HBM bandwidth on this GPU for context: a = b + s c over
+    three 512 MiB FP64 arrays (torch's elementwise kernel), 3 x 8 n bytes per
+    pass, best of `reps` passes timed with events."""
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    for _ in range(3):
+        torch.add(b, c, alpha=0.5, out=a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.add(b, c, alpha=0.5, out=a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b, c
+    return 3 * 8 * n / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(mesh, U, order, fallback, steps=1, single=True):
     """The CPU oracle (as it stands) on the same mesh and state: one full
     SSP-RK3 step over every cell, set-up excluded, all host threads; then
@@ -349,6 +373,8 @@ def main():
     ap.add_argument("--no-cpu-single", action="store_true",
                     help="skip the single-thread oracle timing")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the stream-triad bandwidth measured for context")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-khi", action="store_true", help="skip the KHI TENO3-6 timings")
     ap.add_argument("--no-dmr", action="store_true", help="skip the DMR TENO3-6 timings")
@@ -457,6 +483,10 @@ def main():
         "diagnostics": diag,
         "setup_s": t_setup,
     }
+    if achieved and not args.no_stream:
+        triad = stream_triad_gbs(torch)
+        out["roofline"]["stream_triad_gbs"] = triad
+        out["roofline"]["frac_of_stream_triad"] = achieved / triad
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, teno, inputs)
     if not args.no_batch:
