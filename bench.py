@@ -387,9 +387,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the residual would shard by domain decomposition with one ghost exchange "
-              "per stage; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (a single mesh "
+              "would shard by domain decomposition with one ghost exchange per stage).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
