@@ -215,9 +215,12 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
 
 /* Adjoint of the residual with the selection frozen to `flags`:
  * U_bar = (dR/dU)^T lam.  The reconstruction is linear in U for fixed
- * selection, so this is exact wherever the HLL flux is differentiable.
- * TENO_EARG for CWENO, characteristic variables or a mesh with boundary
- * faces (as for teno_vjp_rk_step). */
+ * selection, so this is exact wherever the HLL flux is differentiable.  On
+ * a mesh with boundary faces the outer states are differentiated through
+ * their conditions (transmissive and reflective follow the inner state,
+ * prescribed states are constants: the ones set when the call runs).
+ * TENO_EARG for CWENO or characteristic variables (as for
+ * teno_vjp_rk_step). */
 int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
                       double* U_bar, void* stream);
 

@@ -1661,7 +1661,6 @@ int oracle_jvp(void* h, const double* U, const uint16_t* flags, const double* v,
   if (!ready(*m)) return -1;
   if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
   if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
-  if (!m->bface.empty()) return fail("no adjoint on a mesh with boundary faces");
   const size_t n4 = 4 * (size_t)m->nc;
   const double hh = 1e-30;
   std::vector<cplx> Uc(n4), Rc(n4);
@@ -1678,7 +1677,6 @@ int oracle_vjp(void* h, const double* U, const uint16_t* flags, const double* la
   if (!ready(*m)) return -1;
   if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
   if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
-  if (!m->bface.empty()) return fail("no adjoint on a mesh with boundary faces");
   const int nq = m->nq, nc = m->nc;
   const size_t n4 = 4 * (size_t)nc;
   // forward face points with the frozen selection
@@ -1686,26 +1684,33 @@ int oracle_vjp(void* h, const double* U, const uint16_t* flags, const double* la
   std::vector<uint16_t> fl(flags, flags + nc);
   for (int i = 0; i < nc; ++i)
     reconstruct_cell(*m, i, U, true, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, nullptr);
-  // gather transposed: Phi_f gets lam_R/|V_R| - lam_L/|V_L|
+  // gather transposed: Phi_f gets lam_R/|V_R| - lam_L/|V_L| (only the inner
+  // cell's term on a boundary face)
   std::vector<double> fpbar(fp.size(), 0.0);
   const double hh = 1e-30;
   for (int f = 0; f < m->nf; ++f) {
     int L = m->fL[f], R = m->fR[f], eL = m->fLe[f], eR = m->fRe[f];
+    const bool bnd = R < 0;
     double pb[4];
-    for (int c = 0; c < 4; ++c) pb[c] = lam[4 * (size_t)R + c] / m->area[R] - lam[4 * (size_t)L + c] / m->area[L];
+    if (!bnd)
+      for (int c = 0; c < 4; ++c) pb[c] = lam[4 * (size_t)R + c] / m->area[R] - lam[4 * (size_t)L + c] / m->area[L];
+    else
+      for (int c = 0; c < 4; ++c) pb[c] = -lam[4 * (size_t)L + c] / m->area[L];
     for (int k = 0; k < nq; ++k) {
       size_t oL = ((size_t)L * 3 * nq + eL * nq + k) * 4;
-      size_t oR = ((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4;
+      size_t oR = bnd ? 0 : ((size_t)R * 3 * nq + eR * nq + (nq - 1 - k)) * 4;
       double sc = m->flen[f] * m->gq_w[k];
-      for (int side = 0; side < 2; ++side)
+      for (int side = 0; side < (bnd ? 1 : 2); ++side)
         for (int c = 0; c < 4; ++c) {
           cplx a[4], b[4], F[4];
           for (int t = 0; t < 4; ++t) {
             a[t] = cplx(fp[oL + t], 0.0);
-            b[t] = cplx(fp[oR + t], 0.0);
+            b[t] = cplx(bnd ? 0.0 : fp[oR + t], 0.0);
           }
           if (side == 0) a[c] += cplx(0.0, hh);
           else b[c] += cplx(0.0, hh);
+          // the outer state of a boundary face follows the (perturbed) inner one
+          if (bnd) boundary_state(*m, m->bidx[f], a, m->fn[2 * f], m->fn[2 * f + 1], b);
           hll_flux(a, b, m->fn[2 * f], m->fn[2 * f + 1], m->prm.gamma, F);
           double acc = 0.0;
           for (int t = 0; t < 4; ++t) acc += pb[t] * (F[t].imag() / hh);

@@ -973,12 +973,12 @@ struct FaceFluxArgs {
 // Outer state of boundary face b at one Gauss point (normal (nx, ny) out of
 // the domain): transmissive copies the inner state, reflective reverses its
 // normal momentum, prescribed takes the given state.
-__device__ __forceinline__ void boundary_state(const FaceFluxArgs& a, int b, const double uL[4],
-                                               double nx, double ny, double uR[4]) {
-  const int kind = a.bkind[b];
+__device__ __forceinline__ void boundary_state(int kind, const double* __restrict__ bstate, int b,
+                                               const double uL[4], double nx, double ny,
+                                               double uR[4]) {
   if (kind == TENO_BC_PRESCRIBED) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) uR[c] = a.bstate[4 * (size_t)b + c];
+    for (int c = 0; c < 4; ++c) uR[c] = bstate[4 * (size_t)b + c];
   } else if (kind == TENO_BC_REFLECTIVE) {
     const double mn = uL[1] * nx + uL[2] * ny;
     uR[0] = uL[0];
@@ -1005,7 +1005,7 @@ __device__ __forceinline__ void face_flux(const FaceFluxArgs& a, int f, int b = 
     const double uL[4] = {l0.x, l0.y, l1.x, l1.y};
     double uR[4];
     if constexpr (BND) {
-      boundary_state(a, b, uL, nrm.x, nrm.y, uR);
+      boundary_state(a.bkind[b], a.bstate, b, uL, nrm.x, nrm.y, uR);
     } else {
       const size_t oR = ((size_t)(eR * NQ + NQ - 1 - k) * a.n_pad + fc.y) * 2;
       const double2 r0 = fp2[oR], r1 = fp2[oR + 1];
@@ -1159,6 +1159,8 @@ struct AdjFaceArgs {
   const double* scale_dev;            // device scalar multiplying lam (nullable = 1)
   double scale;
   double* __restrict__ fpbar;         // [3 nq][n_pad][4]
+  const int* __restrict__ bkind;      // [n_bface] boundary conditions (meshes with open axes)
+  const double* __restrict__ bstate;  // [n_bface][4] prescribed states
   double gamma;
   int n_face, n_pad;
 };
@@ -1197,6 +1199,55 @@ __global__ __launch_bounds__(256) void k_adj_faces(AdjFaceArgs a) {
   const int f = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (f >= a.n_face) return;
   adj_face<NQ>(a, f);
+}
+
+// Boundary faces only (after k_adj_faces, same stream; bf[b] is the face of
+// boundary face b).  Only the inner cell's term enters the face's adjoint,
+// and the outer state follows the inner one through the face's condition,
+// so the inner side also takes the outer side's adjoint through that map,
+// transposed: the identity (transmissive), the mirror I - 2 n n^T of the
+// momentum (reflective, symmetric), nothing (prescribed).  Rewrites every
+// face point of the edge, which k_adj_faces filled as if the cell were on
+// both sides.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_adj_boundary(AdjFaceArgs a, const int* __restrict__ bf,
+                                                      int n_bface) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= n_bface) return;
+  const int f = bf[b];
+  const int4 fc = a.fcell[f];
+  const double2 nrm = a.fgeo[2 * (size_t)f], len = a.fgeo[2 * (size_t)f + 1];
+  const int L = fc.x, eL = fc.z & 3, kind = a.bkind[b];
+  const double sc = a.scale * (a.scale_dev ? *a.scale_dev : 1.0);
+  const double aL = a.vol[L];
+  double pb[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) pb[c] = -sc * (a.lam[(size_t)L * 4 + c] / aL);
+  const double2* fp2 = reinterpret_cast<const double2*>(a.fp);
+  double2* out2 = reinterpret_cast<double2*>(a.fpbar);
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const size_t oL = ((size_t)(eL * NQ + k) * a.n_pad + L) * 2;
+    const double2 l0 = fp2[oL], l1 = fp2[oL + 1];
+    const double uL[4] = {l0.x, l0.y, l1.x, l1.y};
+    double uR[4];
+    boundary_state(kind, a.bstate, b, uL, nrm.x, nrm.y, uR);
+    double gL[4] = {0.0, 0.0, 0.0, 0.0}, gR[4] = {0.0, 0.0, 0.0, 0.0};
+    hll_vjp(uL, uR, nrm.x, nrm.y, a.gamma, pb, gL, gR);
+    if (kind == TENO_BC_TRANSMISSIVE) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gL[c] += gR[c];
+    } else if (kind == TENO_BC_REFLECTIVE) {
+      const double gn = gR[1] * nrm.x + gR[2] * nrm.y;
+      gL[0] += gR[0];
+      gL[1] += gR[1] - 2.0 * gn * nrm.x;
+      gL[2] += gR[2] - 2.0 * gn * nrm.y;
+      gL[3] += gR[3];
+    }
+    const double w = len.x * FaceRule<NQ>::w[k];
+    out2[oL] = make_double2(w * gL[0], w * gL[1]);
+    out2[oL + 1] = make_double2(w * gL[2], w * gL[3]);
+  }
 }
 
 // Phase 2 (one wavefront per tile, one lane per (cell, variable)):

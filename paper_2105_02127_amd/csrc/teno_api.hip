@@ -303,6 +303,8 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   ff.scale_dev = scale_dev;
   ff.scale = scale;
   ff.fpbar = s->fpbar;
+  ff.bkind = s->bkind;
+  ff.bstate = s->bstate;
   ff.gamma = s->prm.gamma;
   ff.n_face = s->n_face;
   ff.n_pad = s->n_pad;
@@ -323,6 +325,9 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 3, st, [&]() {
       hipLaunchKernelGGL((k_adj_faces<decltype(NQ)::value>), dim3(fblocks), dim3(256), 0, st, ff);
+      if (s->n_bface > 0)
+        hipLaunchKernelGGL((k_adj_boundary<decltype(NQ)::value>), dim3((s->n_bface + 255) / 256),
+                           dim3(256), 0, st, ff, (const int*)s->bface, s->n_bface);
       hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
                          dim3(256), (size_t)4 * s->ustride * 4 * sizeof(double), st, ra);
       hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->tbar,
@@ -346,8 +351,8 @@ int check_solver(teno_solver* s) {
   return TENO_OK;
 }
 
-// The adjoint and batches cover periodic meshes only (no boundary-condition
-// Jacobians, no per-face boundary data in the batch descriptors).
+// Batches cover periodic meshes only (no per-face boundary data in the
+// batch descriptors).
 int periodic_only(const teno_solver* s, const char* what) {
   if (s->n_bface > 0)
     return fail(TENO_EARG, std::string(what) + " needs a periodic mesh (this one has boundary faces)");
@@ -715,7 +720,6 @@ int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, co
                       double* U_bar, void* stream) {
   if (int rc = check_solver(s)) return rc;
   if (int rc = needs_selection(s, "vjp_residual")) return rc;
-  if (int rc = periodic_only(s, "vjp_residual")) return rc;
   if (!U || !flags || !lam || !U_bar) return fail(TENO_EARG, "null argument");
   if (U_bar == lam) return fail(TENO_EARG, "U_bar must not alias lam");
   DeviceScope ds(s->device);
@@ -727,7 +731,6 @@ int teno_vjp_rk_step(teno_solver* s, const double* stages, const uint16_t* flags
                      double* lam_in, void* stream) {
   if (int rc = check_solver(s)) return rc;
   if (int rc = needs_selection(s, "vjp_rk_step")) return rc;
-  if (int rc = periodic_only(s, "vjp_rk_step")) return rc;
   if (!stages || !flags3 || !dt_dev || !lam_out || !lam_in) return fail(TENO_EARG, "null argument");
   DeviceScope ds(s->device);
   hipStream_t st = (hipStream_t)stream;

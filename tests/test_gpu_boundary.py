@@ -161,15 +161,49 @@ def test_box_prescribed_states_update_on_device(teno, oracle_mod, torch_cuda):
     assert np.abs(b.host_user(R) - ores["R"]).max() <= REL * _flux_scale(b.U, b.om)
 
 
-def test_box_refuses_adjoint_and_batch(teno, oracle_mod, torch_cuda):
+def test_box_refuses_batch(teno, oracle_mod, torch_cuda):
     from paper_2105_02127_amd.batch import Batch
     b = Box(teno, oracle_mod, torch_cuda, 16, 8, 79, 3)
-    flags = b.sv.empty_flags()
-    b.sv.residual(b.Ud, flags=flags)
-    with pytest.raises(teno.TenoError):
-        b.sv.vjp_residual(b.Ud, flags, b.Ud)
     with pytest.raises(teno.TenoError):
         Batch([b.sv])
+
+
+def _assert_rel(x, y, rel, what):
+    x = np.asarray(x).reshape(-1, 4)
+    y = np.asarray(y).reshape(-1, 4)
+    for v in range(4):
+        err = np.abs(x[:, v] - y[:, v]).max()
+        ref = np.abs(y[:, v]).max()
+        assert err <= rel * ref, f"{what} variable {v}: max err {err:.3e} vs {rel:.0e} * {ref:.3e}"
+
+
+@pytest.mark.parametrize("order,kinds", [(3, (3, 1, 2, 3)), (4, (2, 2, 2, 2)), (5, (1, 3, 2, 1)),
+                                         (6, (1, 1, 1, 1))])
+def test_box_vjp_matches_oracle(teno, oracle_mod, torch_cuda, order, kinds):
+    # the adjoint through transmissive, reflective and prescribed faces:
+    # vjp_residual and vjp_rk_step against the oracle (selection from the
+    # oracle, frozen on both sides)
+    torch = torch_cuda
+    b = Box(teno, oracle_mod, torch, 24, 14, 60 + order, order, kinds=kinds)
+
+    def dev(a):  # user cell order -> the library's, on the device
+        return torch.as_tensor(np.ascontiguousarray(np.asarray(a)[b.perm]), device="cuda")
+
+    flags = b.om.residual(b.U)["flags"]
+    lam = np.random.default_rng(order).normal(size=b.U.shape)
+    ref = b.om.vjp(b.U, flags, lam)
+    got = b.sv.vjp_residual(b.Ud, dev(flags.view(np.int16)), dev(lam))
+    torch.cuda.synchronize()
+    _assert_rel(b.host_user(got), ref, 1e-11, "U_bar")
+    dto = b.om.dt(b.U, 0.4)
+    base = b.om.rk_step(b.U, dto, want_stages=True)
+    ref = b.om.vjp_rk_step(base["stages"], base["flags"], dto, lam)
+    st = torch.stack([dev(base["stages"][k]) for k in range(3)]).contiguous()
+    f3 = torch.stack([dev(base["flags"][k].view(np.int16)) for k in range(3)]).contiguous()
+    dt = torch.full((1,), dto, dtype=torch.float64, device="cuda")
+    got = b.sv.vjp_rk_step(st, f3, dt, dev(lam))
+    torch.cuda.synchronize()
+    _assert_rel(b.host_user(got), ref, 1e-11, "lam_in")
 
 
 def test_full_size_double_mach_sampled(teno, oracle_mod, torch_cuda):

@@ -87,6 +87,12 @@ MUTANTS = [
      "for (int c = 0; c < 4; ++c) uR[c] = uL[c];"),
     ("boundary_kind_swap", "  } else if (m.bkind[b] == 2) {", "  } else if (m.bkind[b] == 1) {"),
     ("stencil_fill_order", "    std::sort(rest.begin(), rest.end());\n", "\n"),
+    ("vjp_boundary_sign", "for (int c = 0; c < 4; ++c) pb[c] = -lam[4 * (size_t)L + c] / m->area[L];",
+     "for (int c = 0; c < 4; ++c) pb[c] = lam[4 * (size_t)L + c] / m->area[L];"),
+    ("vjp_boundary_outer_fixed",
+     "          if (bnd) boundary_state(*m, m->bidx[f], a, m->fn[2 * f], m->fn[2 * f + 1], b);\n",
+     "          if (bnd) { cplx a0[4]; for (int t = 0; t < 4; ++t) a0[t] = cplx(a[t].real(), 0.0);"
+     " boundary_state(*m, m->bidx[f], a0, m->fn[2 * f], m->fn[2 * f + 1], b); }\n"),
 ]
 
 

@@ -1139,3 +1139,30 @@ def test_explosion_conserves_while_the_rim_is_at_rest(oracle_mod, which, order):
     scale = (area[:, None] * np.abs(r["R"])).sum(0)
     assert (np.abs(tot) <= 1e-13 * scale.max()).all(), tot
     assert scale[1] > 1e-3 and scale[3] > 1e-3          # the explosion has started
+
+
+@pytest.mark.parametrize("order,kinds", [(3, [3, 1, 2, 2]), (5, [1, 3, 2, 1]), (4, [2, 2, 2, 2])])
+def test_box_vjp_dot_product_and_differences(oracle_mod, order, kinds):
+    # the adjoint on a mesh with boundaries: the hand-transposed VJP (whose
+    # boundary faces differentiate the outer state through its condition)
+    # against the complex-step JVP of the whole residual, and that JVP
+    # against central differences of the frozen-selection residual
+    u = inputs.conservative(1.1, 0.3, -0.2, 0.9)
+    m, om = _box(oracle_mod, 12, 9, 19 + order, order, 1.3, 1.0, kinds=kinds, state=u, fallback=1)
+    U = inputs.random_lines(m)
+    flags = om.residual(U)["flags"]
+    rng = np.random.default_rng(order)
+    v = rng.normal(size=U.shape)
+    w = rng.normal(size=U.shape)
+    Jv = om.jvp(U, flags, v)
+    JTw = om.vjp(U, flags, w)
+    assert (w * Jv).sum() == pytest.approx((JTw * v).sum(), rel=1e-12)
+    h = 1e-7
+    rp = om.residual(U + h * v, frozen_flags=flags)["R"]
+    rm = om.residual(U - h * v, frozen_flags=flags)["R"]
+    assert np.abs((rp - rm) / (2 * h) - Jv).max() < 1e-6 * np.abs(Jv).max()
+    # the boundary terms matter: dropping them changes the product
+    _, bcells = om.boundary_faces()
+    wb = np.zeros_like(w)
+    wb[bcells] = w[bcells]
+    assert abs((om.vjp(U, flags, wb) * v).sum()) > 1e-3 * abs((JTw * v).sum())
