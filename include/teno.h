@@ -269,8 +269,9 @@ typedef struct teno_batch_tuning {
  * them runs as persistent launches over a shared work list: per stage one
  * reconstruction launch (or one per order, see tuning) over (mesh, tile)
  * items and one flux/update launch over (mesh, 64-cell) items.  The solvers
- * must outlive the batch; their workspaces are reused.  TENO_EARG for CWENO,
- * characteristic variables or meshes with boundary faces. */
+ * must outlive the batch; their workspaces are reused.  Meshes with boundary
+ * faces take their conditions and prescribed states from their solvers.
+ * TENO_EARG for CWENO or characteristic variables. */
 int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out);
 
 int teno_batch_set_tuning(teno_batch* b, const teno_batch_tuning* t);

@@ -1395,9 +1395,11 @@ struct BatchMeshDev {
   const double* U;         // cell averages at the start of the step
   const double* geo;
   double* dt;              // this mesh's step (device scalar)
+  const int* bface;        // [n_bface]: face of each boundary face
   double gamma;
   int pq;                  // order * 10 + face points
   int n_cell;
+  int n_bface;
 };
 
 // Runs reconstruct_tile for pq (any supported pair when PQ == 0, otherwise
@@ -1481,6 +1483,23 @@ __global__ __launch_bounds__(256) void k_batch_face_flux(const BatchMeshDev* __r
     if (d.pq % 10 == 2) face_flux<2>(d.ff, f);
     else face_flux<3>(d.ff, f);
   }
+}
+
+// Boundary faces over (mesh, 64-face chunk) items, one item per wavefront,
+// after k_batch_face_flux: every face, then the boundary faces rewritten
+// with their conditions, as for one mesh.
+__global__ __launch_bounds__(256) void k_batch_boundary_flux(const BatchMeshDev* __restrict__ meshes,
+                                                             const int2* __restrict__ items,
+                                                             int n_items) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w >= n_items) return;
+  const int2 it = items[w];
+  const int m = __builtin_amdgcn_readfirstlane(it.x);
+  const BatchMeshDev& d = meshes[m];
+  const int b = it.y * 64 + lane;
+  if (b >= d.n_bface) return;
+  if (d.pq % 10 == 2) face_flux<2, true>(d.ff, d.bface[b], b);
+  else face_flux<3, true>(d.ff, d.bface[b], b);
 }
 
 // Persistent gather + stage update over (mesh, 64-cell chunk) items.

@@ -351,14 +351,6 @@ int check_solver(teno_solver* s) {
   return TENO_OK;
 }
 
-// Batches cover periodic meshes only (no per-face boundary data in the
-// batch descriptors).
-int periodic_only(const teno_solver* s, const char* what) {
-  if (s->n_bface > 0)
-    return fail(TENO_EARG, std::string(what) + " needs a periodic mesh (this one has boundary faces)");
-  return TENO_OK;
-}
-
 // CWENO (variant 2) has no selection to freeze and hence no adjoint; the
 // frozen and adjoint paths work in conservative variables only.
 int needs_selection(const teno_solver* s, const char* what) {
@@ -836,6 +828,7 @@ struct teno_batch {
   int* start_c = nullptr;
   int2* items_dt = nullptr;
   int* start_dt = nullptr;     // per mesh
+  int2* items_b = nullptr;     // boundary-face items (64-face chunks)
   double* partial = nullptr;
   // launch plan: per reconstruction launch (pq, item offset, wave offset, waves)
   struct RLaunch {
@@ -843,7 +836,7 @@ struct teno_batch {
     int lds_stride;  // LDS per wavefront in int4, the largest of the launch's meshes
   };
   std::vector<RLaunch> rplan;
-  int n_waves_f = 0, n_waves_c = 0, n_items_dt = 0;
+  int n_waves_f = 0, n_waves_c = 0, n_items_dt = 0, n_items_b = 0;
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -970,6 +963,10 @@ int batch_plan(teno_batch* b) {
       ccost.push_back(1.0);
     }
   }
+  std::vector<int2> bitems;
+  for (int m : morder)
+    for (int u = 0; u < (b->sv[m]->n_bface + 63) / 64; ++u) bitems.push_back(make_int2(m, u));
+  b->n_items_b = (int)bitems.size();
   for (int m = 0; m < n; ++m) {
     dstart[m] = (int)ditems.size();
     for (int u = 0; u < (b->sv[m]->n_cell + 255) / 256; ++u) ditems.push_back(make_int2(m, u));
@@ -993,6 +990,7 @@ int batch_plan(teno_batch* b) {
   A(b->items_dt, ditems.size());
   A(b->start_dt, dstart.size());
   A(b->partial, ditems.size());
+  A(b->items_b, bitems.size());
   if (rc) return rc;
   struct Up {
     void* d;
@@ -1005,8 +1003,10 @@ int batch_plan(teno_batch* b) {
              {b->items_c, citems.data(), citems.size() * sizeof(int2)},
              {b->start_c, cstart.data(), cstart.size() * sizeof(int)},
              {b->items_dt, ditems.data(), ditems.size() * sizeof(int2)},
-             {b->start_dt, dstart.data(), dstart.size() * sizeof(int)}};
+             {b->start_dt, dstart.data(), dstart.size() * sizeof(int)},
+             {b->items_b, bitems.data(), bitems.size() * sizeof(int2)}};
   for (auto& u : ups) {
+    if (u.bytes == 0) continue;
     hipError_t e = hipMemcpy(u.d, u.h, u.bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
   }
@@ -1077,6 +1077,8 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
     d.gamma = s->prm.gamma;
     d.pq = s->d.order * 10 + s->d.nq;
     d.n_cell = s->n_cell;
+    d.bface = s->bface;
+    d.n_bface = s->n_bface;
   }
   hipError_t e = hipMemcpyAsync(b->meshes, h.data(), h.size() * sizeof(BatchMeshDev),
                                 hipMemcpyHostToDevice, st);
@@ -1125,6 +1127,9 @@ void batch_launch_step(teno_batch* b, hipStream_t st) {
     batch_launch_recon(b, k, st);
     hipLaunchKernelGGL(k_batch_face_flux, dim3(fblocks), dim3(256), 0, st, b->meshes, b->items_f,
                        b->start_f, b->n_waves_f);
+    if (b->n_items_b > 0)
+      hipLaunchKernelGGL(k_batch_boundary_flux, dim3((b->n_items_b + 3) / 4), dim3(256), 0, st,
+                         b->meshes, b->items_b, b->n_items_b);
     hipLaunchKernelGGL(k_batch_cell_update, dim3(cblocks), dim3(256), 0, st, b->meshes,
                        b->items_c, b->start_c, b->n_waves_c, k);
   }
@@ -1143,7 +1148,6 @@ int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out) 
     for (int k = 0; k < m; ++k)
       if (solvers[k] == solvers[m]) return fail(TENO_EARG, "a solver appears twice in the batch");
     if (solvers[m]->prm.variant == 2) return fail(TENO_EARG, "CWENO meshes cannot be batched");
-    if (int rc = periodic_only(solvers[m], "a batch")) return rc;
     if (solvers[m]->prm.characteristic)
       return fail(TENO_EARG, "meshes in characteristic variables cannot be batched");
   }

@@ -161,11 +161,33 @@ def test_box_prescribed_states_update_on_device(teno, oracle_mod, torch_cuda):
     assert np.abs(b.host_user(R) - ores["R"]).max() <= REL * _flux_scale(b.U, b.om)
 
 
-def test_box_refuses_batch(teno, oracle_mod, torch_cuda):
+@pytest.mark.parametrize("tuning", [
+    dict(order_mode=1, waves_per_cu=0, item_order=1, use_graph=1),
+    dict(order_mode=0, waves_per_cu=4, item_order=0, use_graph=0),
+])
+def test_batch_with_boundaries_equals_single_mesh_steps(teno, oracle_mod, torch_cuda, tuning):
+    # box meshes (every kind of side) batched with a periodic one: each mesh's
+    # step, eager and replayed from the graph twice, equals its own solver's
+    torch = torch_cuda
     from paper_2105_02127_amd.batch import Batch
-    b = Box(teno, oracle_mod, torch_cuda, 16, 8, 79, 3)
-    with pytest.raises(teno.TenoError):
-        Batch([b.sv])
+    boxes = [Box(teno, oracle_mod, torch, 18, 10, 71, 3), Box(teno, oracle_mod, torch, 14, 12, 72, 5),
+             Box(teno, oracle_mod, torch, 20, 9, 73, 6, kinds=(1, 1, 2, 2))]
+    p = inputs.jittered_periodic_mesh(12, 74)
+    plm = teno.Mesh(p.xy, p.tri).setup(order=4, fallback=1)
+    sv = [b.sv for b in boxes] + [teno.Solver(plm)]
+    U = [b.Ud for b in boxes] + [torch.as_tensor(inputs.random_lines(p)[plm.perm], device="cuda")]
+    bt = Batch(sv)
+    bt.set_tuning(**tuning)
+    dt = bt.max_dt(U, 0.4)
+    ref = [u.clone() for u in U]
+    for s, u, d in zip(sv, ref, dt):
+        s.rk_step(u, d.reshape(1).contiguous())
+    for rep in range(2):
+        work = [u.clone() for u in U]
+        bt.rk_step(work, dt)
+        torch.cuda.synchronize()
+        for k, (w, r) in enumerate(zip(work, ref)):
+            assert torch.equal(w, r), f"replay {rep}: mesh {k} differs"
 
 
 def _assert_rel(x, y, rel, what):
