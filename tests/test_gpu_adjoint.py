@@ -1,5 +1,6 @@
 """Adjoint of the SSP-RK3 rollout on the GPU: against the oracle's composed
-step adjoints, and against central finite differences on the adjoint workload
+step adjoints (periodic, and on a box with inflow, outflow and walls), and
+against central finite differences on the adjoint workload
 (TENO4, 256x256x2 cells, 200 steps, checkpoint every 20, loss = sum |V| p^2
 over a seeded disc of radius 0.1, 32 seeded directions, h = 1e-7)."""
 import numpy as np
@@ -47,6 +48,52 @@ def test_rollout_gradient_matches_oracle(oracle_mod, torch_cuda):
     UT, _ = adjoint.rollout(sv, U0d, steps, checkpoint_every=K, dts=dts)
     wd = torch.as_tensor(w[perm], device="cuda")
     (UT * wd).sum().backward()
+    g = np.empty_like(U0)
+    g[perm] = U0d.grad.cpu().numpy()
+    Ug = np.empty_like(U0)
+    Ug[perm] = UT.detach().cpu().numpy()
+    for v in range(4):
+        assert np.abs(Ug[:, v] - U[:, v]).max() <= 1e-12 * np.abs(U[:, v]).max()
+        assert np.abs(g[:, v] - lam[:, v]).max() <= 1e-10 * np.abs(lam[:, v]).max(), v
+
+
+def test_rollout_gradient_on_a_box_matches_oracle(oracle_mod, torch_cuda):
+    # the differentiable rollout on a mesh with walls, inflow and outflow:
+    # the gradient through the boundary conditions against the oracle's
+    # composed step adjoints (same dt sequence, its own selection)
+    torch = torch_cuda
+    from paper_2105_02127_amd import adjoint, teno
+    order, steps, K = 5, 5, 2
+    m = inputs.jittered_box_mesh(16, 10, 107, 1.6, 1.0)
+    U0 = inputs.random_lines(m)
+    lm = teno.Mesh(m.xy, m.tri, period=m.period)
+    om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+    verts, _ = lm.boundary_faces()
+    _, side = inputs.face_sides(m, verts)
+    kind = np.array([teno.BC_PRESCRIBED, teno.BC_TRANSMISSIVE, teno.BC_REFLECTIVE,
+                     teno.BC_REFLECTIVE], np.int32)[side]
+    state = np.tile(inputs.conservative(1.2, 0.4, 0.0, 1.0), (len(verts), 1))
+    lm.set_boundary(kind, state)
+    om.set_boundary(kind, state)
+    lm.setup(order=order, fallback=1)
+    om.setup(oracle_mod.params(order=order, fallback=1))
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    U = U0.copy()
+    recs = []
+    for _ in range(steps):
+        dt = om.dt(U, 0.4)
+        r = om.rk_step(U, dt, want_stages=True)
+        recs.append((r["stages"], r["flags"], dt))
+        U = r["U"]
+    w = np.random.default_rng(9).normal(size=U.shape)
+    lam = w.copy()
+    for st, fl, dt in reversed(recs):
+        lam = om.vjp_rk_step(st, fl, dt, lam)
+    dts = torch.tensor([d for _, _, d in recs], dtype=torch.float64, device="cuda")
+    U0d = torch.as_tensor(U0[perm], device="cuda").requires_grad_(True)
+    UT, _ = adjoint.rollout(sv, U0d, steps, checkpoint_every=K, dts=dts)
+    (UT * torch.as_tensor(w[perm], device="cuda")).sum().backward()
     g = np.empty_like(U0)
     g[perm] = U0d.grad.cpu().numpy()
     Ug = np.empty_like(U0)
