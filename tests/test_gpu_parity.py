@@ -402,10 +402,15 @@ def test_vjp_rk_step_matches_oracle(teno, oracle_mod, torch_cuda):
 # --------------------------------------------------------------------------
 # full-size workloads: sampled cells the oracle computes one by one
 # --------------------------------------------------------------------------
-def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0):
-    w, m, U = inputs.make_workload(key)
-    print(f"[full-size] {w['name']} cells={m.n_cell} characteristic={characteristic}", flush=True)
+def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0, n=None):
+    w, m, U = inputs.make_workload(key, n=n)
+    print(f"[full-size] {w['name']} n={w['n']} cells={m.n_cell} characteristic={characteristic}",
+          flush=True)
     lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1, characteristic=characteristic)
+    info = lm.info()
+    if n is not None and n > 1024:
+        # past 2^31 operator entries: every offset into M must be 64-bit
+        assert info.matrix_doubles_per_cell * m.n_cell > 2 ** 31
     sv = teno.Solver(lm)
     perm = lm.perm
     om = oracle_mod.OracleMesh(m.xy, m.tri)
@@ -461,6 +466,12 @@ def test_full_size_teno5_lines_sampled(teno, oracle_mod, torch_cuda):
 
 def test_full_size_teno6_wavejump_sampled(teno, oracle_mod, torch_cuda):
     _sampled(teno, oracle_mod, torch_cuda, 3, n_sample=64)
+
+
+def test_teno6_past_2e31_operator_entries_sampled(teno, oracle_mod, torch_cuda):
+    # the largest case: 1050^2 x 2 = 2,205,000 cells at order 6, whose
+    # operators hold more than 2^31 doubles (17.4 GB)
+    _sampled(teno, oracle_mod, torch_cuda, 3, n_sample=48, n=1050)
 
 
 def test_full_size_teno5_khi_sampled(teno, oracle_mod, torch_cuda):
