@@ -149,8 +149,11 @@ int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
       ev = s->pool.back();
       s->pool.pop_back();
     } else {
-      if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess)
+      if (hipEventCreate(&ev.first) != hipSuccess) return fail(TENO_EHIP, "hipEventCreate failed");
+      if (hipEventCreate(&ev.second) != hipSuccess) {
+        (void)hipEventDestroy(ev.first);
         return fail(TENO_EHIP, "hipEventCreate failed");
+      }
     }
     (void)hipEventRecord(ev.first, st);
   }
@@ -164,7 +167,6 @@ int timed(teno_solver* s, int kind, hipStream_t st, F&& launch) {
   return TENO_OK;
 }
 
-// Doubles of one stage's face states in the library layout [3 nq][n_pad][4].
 // chi counts as a near tie when |chi / C_T - 1| <= tie_rel; an empty window
 // when C_T = 0 (the linear scheme has no ties).
 static void set_tie_window(ReconArgs& a) {
@@ -177,6 +179,7 @@ static void set_tie_window(ReconArgs& a) {
   }
 }
 
+// Doubles of one stage's face states in the library layout [3 nq][n_pad][4].
 static size_t face_state_doubles(const teno_solver* s) { return (size_t)3 * s->d.nq * s->n_pad * 4; }
 
 // fp: face-state buffer of the launch (library layout), nullptr = the
