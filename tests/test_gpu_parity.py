@@ -468,6 +468,48 @@ def test_full_size_teno6_wavejump_sampled(teno, oracle_mod, torch_cuda):
     _sampled(teno, oracle_mod, torch_cuda, 3, n_sample=64)
 
 
+def test_full_size_teno5_lines_two_rk_steps(teno, oracle_mod, torch_cuda):
+    # the headline workload at its size (524,288 cells), in the bench's
+    # launch configuration: two whole SSP-RK3 steps on both sides (the
+    # oracle's dt), every stage of every cell compared.  A flag flipped at a
+    # near tie would change its cell's stencil, so the states are compared
+    # only when the oracle reports none (it reports how many it saw).
+    torch = torch_cuda
+    w, m, U = inputs.make_workload(2)
+    print(f"[full-size trajectory] {w['name']} cells={m.n_cell}", flush=True)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1)
+    sv = teno.Solver(lm)
+    perm = lm.perm
+    om = oracle_mod.OracleMesh(m.xy, m.tri)
+    om.setup(oracle_mod.params(order=w["order"], fallback=1))
+    Ud = torch.as_tensor(U[perm], device="cuda")
+    stages = torch.empty((3, m.n_cell, 4), dtype=torch.float64, device="cuda")
+    flags3 = sv.empty_flags(3)
+
+    def user(t):
+        a = t.cpu().numpy()
+        out = np.empty_like(a)
+        out[..., perm, :] = a
+        return out
+
+    for step in range(2):
+        dto = om.dt(U, 0.4)
+        ref = om.rk_step(U, dto, want_stages=True)
+        sv.rk_step(Ud, torch.full((1,), dto, dtype=torch.float64, device="cuda"),
+                   flags3=flags3, stages=stages)
+        torch.cuda.synchronize()
+        gfl = np.empty((3, m.n_cell), np.uint16)
+        gfl[:, perm] = flags3.cpu().numpy().view(np.uint16)
+        for k in range(3):
+            check_flags(gfl[k], ref["flags"][k], ref["diag"])
+        assert ref["diag"]["near_ties"] == 0, "near ties: states may differ where a flag flipped"
+        got = user(stages)
+        for k in range(3):
+            assert_states(got[k], ref["stages"][k], what=f"step {step} stage {k}")
+        U = ref["U"]
+        assert_states(user(Ud[None])[0], U, what=f"step {step}")
+
+
 def test_teno6_past_2e31_operator_entries_sampled(teno, oracle_mod, torch_cuda):
     # the largest case: 1050^2 x 2 = 2,205,000 cells at order 6, whose
     # operators hold more than 2^31 doubles (17.4 GB)
