@@ -73,15 +73,19 @@ def lib():
         L.oracle_set_boundary.argtypes = [vp, ip, dp]
         L.oracle_char_basis.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.oracle_cweno_weights.argtypes = [C.POINTER(Params), dp, dp, dp]
-        L.oracle_reconstruct_cells.argtypes = [vp, dp, C.c_int, ip, dp, up, dp, C.POINTER(Diag)]
-        L.oracle_residual.argtypes = [vp, dp, dp, up, C.c_int, dp, C.POINTER(Diag)]
+        L.oracle_reconstruct_cells.argtypes = [vp, dp, C.c_int, ip, dp, up, dp, C.POINTER(Diag),
+                                               up]
+        L.oracle_residual.argtypes = [vp, dp, dp, up, C.c_int, dp, C.POINTER(Diag), up]
         L.oracle_residual_cells.argtypes = [vp, dp, C.c_int, ip, dp, up]
         L.oracle_dt.restype = C.c_double
         L.oracle_dt.argtypes = [vp, dp, C.c_double]
-        L.oracle_rk_step.argtypes = [vp, dp, dp, C.c_double, up, C.c_int, dp, C.POINTER(Diag)]
+        L.oracle_rk_step.argtypes = [vp, dp, dp, C.c_double, up, C.c_int, dp, C.POINTER(Diag),
+                                     up]
         L.oracle_jvp.argtypes = [vp, dp, up, dp, dp]
         L.oracle_vjp.argtypes = [vp, dp, up, dp, dp]
         L.oracle_vjp_rk_step.argtypes = [vp, dp, up, C.c_double, dp, dp]
+        L.oracle_vjp_scale.argtypes = [vp, dp, up, dp, dp]
+        L.oracle_vjp_rk_step_scale.argtypes = [vp, dp, up, C.c_double, dp, dp]
         L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_get_threads.restype = C.c_int
         L.oracle_default_params.argtypes = [C.POINTER(Params)]
@@ -231,20 +235,25 @@ class OracleMesh:
     def reconstruct_cells(self, U, cells):
         """(fp [n][3][nq][4], flags, beta, diag).  flags: [n], or [n][3]
         (one per local edge) in characteristic variables, where beta is
-        None."""
+        None.  diag["tie_mask"] is laid out like flags: nibble v is 0xF
+        where the selection of variable v met a near tie."""
         U = _f64(U)
         c = np.ascontiguousarray(cells, dtype=np.int32)
         fp = np.empty((c.size, 3, self.nq, 4))
         fl = np.empty((c.size, 3) if self.characteristic else c.size, dtype=np.uint16)
+        ties = np.zeros_like(fl)
         beta = np.empty((c.size, 4, 4))
         dg = Diag(0, -1, 0, 0, 0)
         _check(lib().oracle_reconstruct_cells(self.h, _d(U), c.size, _i(c), _d(fp), _u(fl),
-                                              _d(beta), C.byref(dg)))
-        return fp, fl, (None if self.characteristic else beta), dg.as_dict()
+                                              _d(beta), C.byref(dg), _u(ties)))
+        d = dg.as_dict()
+        d["tie_mask"] = ties
+        return fp, fl, (None if self.characteristic else beta), d
 
     def residual(self, U, frozen_flags=None, want_fp=False):
         """flags: [n_cell], or [3][n_cell] (per local edge) in
-        characteristic variables."""
+        characteristic variables; diag["tie_mask"] is laid out like flags
+        (nibble v = 0xF where variable v met a near tie)."""
         U = _f64(U)
         R = np.empty_like(U)
         if frozen_flags is not None:
@@ -253,11 +262,13 @@ class OracleMesh:
             fl = np.empty((3, self.n_cell) if self.characteristic else self.n_cell,
                           dtype=np.uint16)
         fp = np.empty((self.n_cell, 3, self.nq, 4)) if want_fp else None
+        ties = np.zeros(fl.shape, dtype=np.uint16)
         dg = Diag(0, -1, 0, 0, 0)
         _check(lib().oracle_residual(self.h, _d(U), _d(R), _u(fl),
                                      1 if frozen_flags is not None else 0,
-                                     None if fp is None else _d(fp), C.byref(dg)))
+                                     None if fp is None else _d(fp), C.byref(dg), _u(ties)))
         out = dict(R=R, flags=fl, diag=dg.as_dict())
+        out["diag"]["tie_mask"] = ties
         if want_fp:
             out["fp"] = fp
         return out
@@ -282,11 +293,13 @@ class OracleMesh:
             fl = np.empty((3, 3, self.n_cell) if self.characteristic else (3, self.n_cell),
                           dtype=np.uint16)
         st = np.empty((3,) + U.shape) if want_stages else None
+        ties = np.zeros(fl.shape, dtype=np.uint16)
         dg = Diag(0, -1, 0, 0, 0)
         _check(lib().oracle_rk_step(self.h, _d(U), _d(out), float(dt), _u(fl),
                                     1 if frozen_flags3 is not None else 0,
-                                    None if st is None else _d(st), C.byref(dg)))
+                                    None if st is None else _d(st), C.byref(dg), _u(ties)))
         res = dict(U=out, flags=fl, diag=dg.as_dict())
+        res["diag"]["tie_mask"] = ties
         if want_stages:
             res["stages"] = st
         return res
@@ -304,6 +317,26 @@ class OracleMesh:
         ub = np.empty_like(U)
         _check(lib().oracle_vjp(self.h, _d(U), _u(fl), _d(lam), _d(ub)))
         return ub
+
+    def vjp_scale(self, U, flags, lam):
+        """Comparison scale of vjp(U, flags, lam): per cell and variable, the
+        summed magnitudes of the terms the adjoint adds there (see
+        oracle_vjp_scale)."""
+        U, lam = _f64(U), _f64(lam)
+        fl = np.ascontiguousarray(flags, dtype=np.uint16)
+        S = np.empty_like(U)
+        _check(lib().oracle_vjp_scale(self.h, _d(U), _u(fl), _d(lam), _d(S)))
+        return S
+
+    def vjp_rk_step_scale(self, stages, flags3, dt, lam_out):
+        """Comparison scale of vjp_rk_step (magnitudes through the stage
+        chain); lam_out may itself be a scale of the previous step."""
+        st, lam_out = _f64(stages), _f64(lam_out)
+        fl = np.ascontiguousarray(flags3, dtype=np.uint16)
+        S = np.empty_like(lam_out)
+        _check(lib().oracle_vjp_rk_step_scale(self.h, _d(st), _u(fl), float(dt), _d(lam_out),
+                                              _d(S)))
+        return S
 
     def vjp_rk_step(self, stages, flags3, dt, lam_out):
         st, lam_out = _f64(stages), _f64(lam_out)

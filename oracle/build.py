@@ -9,8 +9,10 @@ SRC = os.path.join(HERE, "teno_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
 # No FMA contraction and no fast-math: the oracle evaluates every expression
-# as written, in IEEE double precision.
-CMD = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+# as written, in IEEE double precision (so -O3 changes its speed, never its
+# results).  No -march=native: the library built on one host is loaded on
+# another, whose CPU may lack the build host's instruction set.
+CMD = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
        "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", LIB, SRC]
 
 

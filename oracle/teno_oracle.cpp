@@ -694,10 +694,10 @@ void cweno_combine(const double w[4], const double d[4], const std::vector<T> co
 // ---------------------------------------------------------------------------
 template <class T>
 void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& flags,
-                      T* fp, double* beta_out, oracle_diag* dg) {
+                      T* fp, double* beta_out, oracle_diag* dg, uint16_t* ties_out = nullptr) {
   const CellData& cd = m.cd[i];
   const int nb = m.big.n(), ns = m.small.n();
-  uint16_t out_flags = 0;
+  uint16_t out_flags = 0, tie_nib = 0;
   for (int v = 0; v < 4; ++v) {
     T u0 = U[4 * i + v];
     std::vector<T> coef[4];
@@ -737,6 +737,7 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
       if (beta_out) for (int k = 0; k < 4; ++k) beta_out[4 * v + k] = beta[k];
       Sel s = select(beta, m.prm);
       f4 = s.flags;
+      if (s.ties) tie_nib |= (uint16_t)(0xFu << (4 * v));
       if (dg) {
         dg->near_ties += s.ties;
         if (f4 & 8u) dg->large_kept++;
@@ -774,6 +775,7 @@ void reconstruct_cell(const Mesh& m, int i, const T* U, bool frozen, uint16_t& f
     }
   }
   flags = out_flags;
+  if (ties_out) *ties_out = tie_nib;
 }
 
 // +1 when cell i is the L side of the face on its local edge e (the face
@@ -859,7 +861,7 @@ void edge_normal(const Mesh& m, int i, int e, double& nx, double& ny) {
 // flags of local edge e (bit 4v+3: large stencil kept for characteristic
 // variable v, bits 4v..4v+2: small stencils kept).
 void reconstruct_cell_char(const Mesh& m, int i, const double* U, uint16_t* flags3, double* fp,
-                           oracle_diag* dg) {
+                           oracle_diag* dg, uint16_t* ties3 = nullptr) {
   const CellData& cd = m.cd[i];
   const int nb = m.big.n(), ns = m.small.n();
   // least-squares coefficients of the conservative variables (linear in
@@ -871,7 +873,7 @@ void reconstruct_cell_char(const Mesh& m, int i, const double* U, uint16_t* flag
     double nx, ny, R[16], L[16];
     edge_normal(m, i, e, nx, ny);
     char_basis(u0, nx, ny, m.prm.gamma, R, L);
-    uint16_t fe = 0;
+    uint16_t fe = 0, te = 0;
     std::vector<double> dw[4];  // per characteristic variable: value minus mean at the points
     for (int v = 0; v < 4; ++v) {
       std::vector<double> wc[4];
@@ -893,6 +895,7 @@ void reconstruct_cell_char(const Mesh& m, int i, const double* U, uint16_t* flag
           dg->near_ties += s.ties;
           if (s.flags & 8u) dg->large_kept++;
         }
+        if (s.ties) te |= (uint16_t)(0xFu << (4 * v));
         fe |= (uint16_t)(s.flags << (4 * v));
         teno_combine(s.flags, wc, nb, ns, abar);
       }
@@ -904,6 +907,7 @@ void reconstruct_cell_char(const Mesh& m, int i, const double* U, uint16_t* flag
       }
     }
     flags3[e] = fe;
+    if (ties3) ties3[e] = te;
     // back to conservative variables: U = U_0 + R dw
     for (int kq = 0; kq < m.nq; ++kq)
       for (int c = 0; c < 4; ++c) {
@@ -1034,11 +1038,12 @@ void assemble(const Mesh& m, const std::vector<T>& phi, int i, T* Ri) {
 
 template <class T>
 void residual_full(const Mesh& m, const T* U, T* R, uint16_t* flags, bool frozen,
-                   double* fp_out, oracle_diag* dg) {
+                   double* fp_out, oracle_diag* dg, uint16_t* ties = nullptr) {
   const int nq = m.nq;
   const bool chr = m.prm.characteristic != 0;  // flags per local edge, never frozen
   std::vector<T> fp((size_t)m.nc * 3 * nq * 4);
   std::vector<uint16_t> fl((size_t)m.nc * (chr ? 3 : 1), 0);
+  std::vector<uint16_t> tl(fl.size(), 0);
   if (frozen) for (int i = 0; i < m.nc; ++i) fl[i] = flags[i];
   int64_t nt = 0, lk = 0, fb = 0, nbad = 0, first = m.nc;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : nt, lk, fb, nbad) reduction(min : first)
@@ -1046,9 +1051,11 @@ void residual_full(const Mesh& m, const T* U, T* R, uint16_t* flags, bool frozen
     oracle_diag local{0, -1, 0, 0, 0};
     if constexpr (std::is_same<T, double>::value) {
       if (chr)
-        reconstruct_cell_char(m, i, U, &fl[3 * (size_t)i], &fp[(size_t)i * 3 * nq * 4], &local);
+        reconstruct_cell_char(m, i, U, &fl[3 * (size_t)i], &fp[(size_t)i * 3 * nq * 4], &local,
+                              &tl[3 * (size_t)i]);
       else
-        reconstruct_cell(m, i, U, frozen, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, &local);
+        reconstruct_cell(m, i, U, frozen, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, &local,
+                         &tl[i]);
     } else {
       reconstruct_cell(m, i, U, frozen, fl[i], &fp[(size_t)i * 3 * nq * 4], nullptr, &local);
     }
@@ -1078,6 +1085,14 @@ void residual_full(const Mesh& m, const T* U, T* R, uint16_t* flags, bool frozen
         for (int i = 0; i < m.nc; ++i) flags[(size_t)e * m.nc + i] = fl[3 * (size_t)i + e];
     } else {
       for (int i = 0; i < m.nc; ++i) flags[i] = fl[i];
+    }
+  }
+  if (ties) {
+    if (chr) {
+      for (int e = 0; e < 3; ++e)
+        for (int i = 0; i < m.nc; ++i) ties[(size_t)e * m.nc + i] = tl[3 * (size_t)i + e];
+    } else {
+      for (int i = 0; i < m.nc; ++i) ties[i] = tl[i];
     }
   }
 }
@@ -1482,9 +1497,12 @@ void oracle_hll(const double* uL, const double* uR, double nx, double ny, double
 
 // Reconstructed face-point states of listed cells: fp [n][3][nq][4],
 // flags [n] ([n][3], one per local edge, in characteristic variables), beta
-// [n][4 vars][4 stencils] (nullable; conservative variables only).
+// [n][4 vars][4 stencils] (nullable; conservative variables only).  ties
+// (nullable, laid out like flags): nibble v is 0xF where the selection of
+// variable v met a near tie (Sec. 3.3 cutoff; |chi/C_T - 1| <= tie_rel for
+// one of its chi), else 0.
 int oracle_reconstruct_cells(void* h, const double* U, int n, const int* cells, double* fp,
-                             uint16_t* flags, double* beta, oracle_diag* dg) {
+                             uint16_t* flags, double* beta, oracle_diag* dg, uint16_t* ties) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   if (oracle_prepare_cells(h, n, cells) != 0) return -1;
@@ -1494,15 +1512,18 @@ int oracle_reconstruct_cells(void* h, const double* U, int n, const int* cells, 
   for (int t = 0; t < n; ++t) {
     oracle_diag local{0, -1, 0, 0, 0};
     if (m->prm.characteristic) {
-      uint16_t fl3[3] = {0, 0, 0};
-      reconstruct_cell_char(*m, cells[t], U, fl3, &fp[(size_t)t * 3 * nq * 4], &local);
-      if (flags)
-        for (int e = 0; e < 3; ++e) flags[3 * (size_t)t + e] = fl3[e];
+      uint16_t fl3[3] = {0, 0, 0}, tl3[3] = {0, 0, 0};
+      reconstruct_cell_char(*m, cells[t], U, fl3, &fp[(size_t)t * 3 * nq * 4], &local, tl3);
+      for (int e = 0; e < 3; ++e) {
+        if (flags) flags[3 * (size_t)t + e] = fl3[e];
+        if (ties) ties[3 * (size_t)t + e] = tl3[e];
+      }
     } else {
-      uint16_t fl = 0;
+      uint16_t fl = 0, tl = 0;
       reconstruct_cell(*m, cells[t], U, false, fl, &fp[(size_t)t * 3 * nq * 4],
-                       beta ? &beta[(size_t)t * 16] : nullptr, &local);
+                       beta ? &beta[(size_t)t * 16] : nullptr, &local, &tl);
       if (flags) flags[t] = fl;
+      if (ties) ties[t] = tl;
     }
     nt += local.near_ties;
     lk += local.large_kept;
@@ -1520,16 +1541,18 @@ int oracle_reconstruct_cells(void* h, const double* U, int n, const int* cells, 
 
 // Full residual R[nc][4]; flags[nc] out (or in when frozen=1; in
 // characteristic variables [3][nc], one per local edge, out only); fp_out
-// [nc][3][nq][4] nullable; diag nullable.
+// [nc][3][nq][4] nullable; diag nullable; ties nullable, laid out like
+// flags, the near-tie nibbles of each cell (all 0 when frozen).
 int oracle_residual(void* h, const double* U, double* R, uint16_t* flags, int frozen,
-                    double* fp_out, oracle_diag* dg) {
+                    double* fp_out, oracle_diag* dg, uint16_t* ties) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   if (frozen && !flags) return fail("frozen selection needs flags");
   if (frozen && m->prm.characteristic) return fail("no frozen selection in characteristic variables");
   for (int i = 0; i < m->nc; ++i)
     if (!m->cd[i].built) return fail("oracle_setup(all=1) required for the full residual");
-  residual_full(*m, U, R, flags, frozen != 0, fp_out, dg);
+  residual_full(*m, U, R, flags, frozen != 0, fp_out, dg, frozen ? nullptr : ties);
+  if (frozen && ties) std::fill(ties, ties + m->nc, (uint16_t)0);
   return 0;
 }
 
@@ -1620,9 +1643,10 @@ double oracle_dt(void* h, const double* U, double cfl) {
 
 // One SSP-RK3 step (Sec. 2.1, time discretisation); flags3 [3][nc] nullable
 // (out, or in when frozen=1; [3][3][nc] out in characteristic variables);
-// stages [3][nc][4] nullable (stage inputs).
+// stages [3][nc][4] nullable (stage inputs); ties3 nullable, laid out like
+// flags3, the near-tie nibbles of each stage.
 int oracle_rk_step(void* h, const double* U, double* Uout, double dt, uint16_t* flags3,
-                   int frozen, double* stages, oracle_diag* dg) {
+                   int frozen, double* stages, oracle_diag* dg, uint16_t* ties3) {
   Mesh* m = (Mesh*)h;
   if (!ready(*m)) return -1;
   const size_t n4 = 4 * (size_t)m->nc;
@@ -1638,16 +1662,17 @@ int oracle_rk_step(void* h, const double* U, double* Uout, double dt, uint16_t* 
   auto keep = [&](int s) {
     if (flags3 && !frozen) std::copy(fl.begin(), fl.end(), flags3 + (size_t)s * nfl);
   };
+  auto tie = [&](int s) -> uint16_t* { return ties3 ? ties3 + (size_t)s * nfl : nullptr; };
   if (stages) std::copy(U, U + n4, stages);
-  if (oracle_residual(h, U, R.data(), stage_flags(0), frozen, nullptr, dg)) return -1;
+  if (oracle_residual(h, U, R.data(), stage_flags(0), frozen, nullptr, dg, tie(0))) return -1;
   keep(0);
   for (size_t t = 0; t < n4; ++t) U1[t] = U[t] + dt * R[t];
   if (stages) std::copy(U1.begin(), U1.end(), stages + n4);
-  if (oracle_residual(h, U1.data(), R.data(), stage_flags(1), frozen, nullptr, dg)) return -1;
+  if (oracle_residual(h, U1.data(), R.data(), stage_flags(1), frozen, nullptr, dg, tie(1))) return -1;
   keep(1);
   for (size_t t = 0; t < n4; ++t) U2[t] = 0.75 * U[t] + 0.25 * U1[t] + 0.25 * (dt * R[t]);
   if (stages) std::copy(U2.begin(), U2.end(), stages + 2 * n4);
-  if (oracle_residual(h, U2.data(), R.data(), stage_flags(2), frozen, nullptr, dg)) return -1;
+  if (oracle_residual(h, U2.data(), R.data(), stage_flags(2), frozen, nullptr, dg, tie(2))) return -1;
   keep(2);
   const double a = 1.0 / 3.0, b = 2.0 / 3.0;
   for (size_t t = 0; t < n4; ++t) Uout[t] = a * U[t] + b * U2[t] + b * (dt * R[t]);
@@ -1758,6 +1783,130 @@ int oracle_vjp(void* h, const double* U, const uint16_t* flags, const double* la
       }
     }
   }
+  return 0;
+}
+
+// Comparison scale of the residual's adjoint (test infrastructure: it sets
+// the tolerance of parity tests, it is not part of the method).  S[i][v] is
+// the sum of the magnitudes of every term the adjoint adds into U_bar[i][v],
+// each term bounded through its own factors: at a face point,
+// |A| w_k sum_t |Phi_bar_t| |dF_t/du_c| (the flux derivative by complex
+// step, exact); for a stencil row s, |V'_s| sum_l |pinv(A)_ls| |abar_l|, with
+// abar_l = sum over the face points of |psi_l| times the face-point term.  A
+// sum of these terms formed in any order, from factors that carry a few
+// rounding errors each, is exact to a small multiple of the unit roundoff
+// times S, which is what the GPU adjoint is held to.
+int oracle_vjp_scale(void* h, const double* U, const uint16_t* flags, const double* lam, double* S) {
+  Mesh* m = (Mesh*)h;
+  if (!ready(*m)) return -1;
+  if (m->prm.variant == 2) return fail("CWENO has no frozen selection: no adjoint");
+  if (m->prm.characteristic) return fail("no adjoint in characteristic variables");
+  const int nq = m->nq, nc = m->nc;
+  std::vector<double> fp((size_t)nc * 3 * nq * 4);
+  for (int i = 0; i < nc; ++i) {
+    uint16_t fi = flags[i];
+    reconstruct_cell(*m, i, U, true, fi, &fp[(size_t)i * 3 * nq * 4], nullptr, nullptr);
+  }
+  std::vector<double> gabs(fp.size(), 0.0);
+  const double step = 1e-30;
+  for (int f = 0; f < m->nf; ++f) {
+    const int cl = m->fL[f], cr = m->fR[f];
+    const bool open_face = cr < 0;
+    double w[4];
+    for (int c = 0; c < 4; ++c) {
+      w[c] = std::fabs(lam[4 * (size_t)cl + c]) / m->area[cl];
+      if (!open_face) w[c] += std::fabs(lam[4 * (size_t)cr + c]) / m->area[cr];
+    }
+    for (int k = 0; k < nq; ++k) {
+      const size_t pl = ((size_t)cl * 3 * nq + m->fLe[f] * nq + k) * 4;
+      const size_t pr = open_face ? 0 : ((size_t)cr * 3 * nq + m->fRe[f] * nq + (nq - 1 - k)) * 4;
+      const double wk = m->flen[f] * m->gq_w[k];
+      for (int side = 0; side < (open_face ? 1 : 2); ++side)
+        for (int c = 0; c < 4; ++c) {
+          cplx ul[4], ur[4], F[4];
+          for (int t = 0; t < 4; ++t) {
+            ul[t] = cplx(fp[pl + t], side == 0 && t == c ? step : 0.0);
+            ur[t] = cplx(open_face ? 0.0 : fp[pr + t], side == 1 && t == c ? step : 0.0);
+          }
+          if (open_face) boundary_state(*m, m->bidx[f], ul, m->fn[2 * f], m->fn[2 * f + 1], ur);
+          hll_flux(ul, ur, m->fn[2 * f], m->fn[2 * f + 1], m->prm.gamma, F);
+          double sum = 0.0;
+          for (int t = 0; t < 4; ++t) sum += w[t] * std::fabs(F[t].imag() / step);
+          gabs[(side == 0 ? pl : pr) + c] += wk * sum;
+        }
+    }
+  }
+  std::fill(S, S + 4 * (size_t)nc, 0.0);
+  const int nb = m->big.n(), ns = m->small.n();
+  for (int i = 0; i < nc; ++i) {
+    const CellData& cd = m->cd[i];
+    // pinv(A) of each stencil, column s = the solve of unit vector e_s
+    std::vector<double> pinv[4];
+    for (int k = 0; k < 4; ++k) {
+      const QR& q = cd.st[k].qr;
+      pinv[k].assign((size_t)q.m * q.n, 0.0);
+      std::vector<double> e(q.m, 0.0), x(q.n);
+      for (int r = 0; r < q.m; ++r) {
+        e[r] = 1.0;
+        qr_solve(q, e.data(), x.data());
+        e[r] = 0.0;
+        for (int l = 0; l < q.n; ++l) pinv[k][(size_t)r * q.n + l] = x[l];
+      }
+    }
+    for (int v = 0; v < 4; ++v) {
+      const unsigned f4 = (flags[i] >> (4 * v)) & 0xFu;
+      std::vector<double> aabs(nb, 0.0);
+      for (int e = 0; e < 3; ++e)
+        for (int kq = 0; kq < nq; ++kq) {
+          const double g = gabs[((size_t)i * 3 * nq + e * nq + kq) * 4 + v];
+          double xi, eta;
+          face_point(e, m->gq_t[kq], xi, eta);
+          S[4 * (size_t)i + v] += g;
+          for (int l = 0; l < nb; ++l) aabs[l] += g * std::fabs(psi(m->big, l, xi, eta));
+        }
+      const int kept_small = (int)((f4 & 1u) + ((f4 >> 1) & 1u) + ((f4 >> 2) & 1u));
+      for (int k = 0; k < 4; ++k) {
+        double wgt;
+        if (k == 3) {
+          if (!(f4 & 8u)) continue;
+          wgt = 1.0;
+        } else {
+          if ((f4 & 8u) || !(f4 & (1u << k))) continue;
+          wgt = 1.0 / (double)kept_small;
+        }
+        const Stencil& St = cd.st[k];
+        const int nco = k == 3 ? nb : ns;
+        for (int r = 0; r < St.qr.m; ++r) {
+          double t = 0.0;
+          for (int l = 0; l < nco; ++l) t += std::fabs(pinv[k][(size_t)r * St.qr.n + l]) * aabs[l];
+          t *= wgt * St.vol[r];
+          S[4 * (size_t)St.cells[r] + v] += t;
+          S[4 * (size_t)i + v] += t;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+// The same comparison scale through one SSP-RK3 step: the step adjoint's
+// stage chain with every coefficient and adjoint replaced by its magnitude.
+int oracle_vjp_rk_step_scale(void* h, const double* stages, const uint16_t* flags3, double dt,
+                             const double* lam_out, double* S_in) {
+  Mesh* m = (Mesh*)h;
+  if (!ready(*m)) return -1;
+  const size_t nc = m->nc, n4 = 4 * nc;
+  std::vector<double> lo(n4), q(n4), s2(n4), s1(n4), s0(n4), tot(n4);
+  for (size_t t = 0; t < n4; ++t) lo[t] = std::fabs(lam_out[t]);
+  for (size_t t = 0; t < n4; ++t) q[t] = (2.0 / 3.0) * dt * lo[t];
+  if (oracle_vjp_scale(h, stages + 2 * n4, flags3 + 2 * nc, q.data(), s2.data())) return -1;
+  for (size_t t = 0; t < n4; ++t) s2[t] += (2.0 / 3.0) * lo[t];
+  for (size_t t = 0; t < n4; ++t) q[t] = 0.25 * dt * s2[t];
+  if (oracle_vjp_scale(h, stages + n4, flags3 + nc, q.data(), s1.data())) return -1;
+  for (size_t t = 0; t < n4; ++t) s1[t] += 0.25 * s2[t];
+  for (size_t t = 0; t < n4; ++t) q[t] = dt * s1[t];
+  if (oracle_vjp_scale(h, stages, flags3, q.data(), s0.data())) return -1;
+  for (size_t t = 0; t < n4; ++t) S_in[t] = lo[t] / 3.0 + 0.75 * s2[t] + s1[t] + s0[t];
   return 0;
 }
 

@@ -476,12 +476,16 @@ def test_residual_cells_match_full(oracle_mod):
 # --------------------------------------------------------------------------
 # smooth data: TENO restores the linear scheme exactly (Sec. 5.1 tables)
 # --------------------------------------------------------------------------
-def test_teno_equals_linear_on_smooth_wave(oracle_mod):
+@pytest.mark.parametrize("order", [3, 4, 5, 6])
+def test_teno_equals_linear_on_smooth_wave(oracle_mod, order):
+    # Sec. 5.1: the TENO rows of every accuracy table equal the Linear rows;
+    # on the smooth workload every selection keeps the large stencil, so 10
+    # steps of TENO and of the linear scheme agree bit for bit
     w, m, U = inputs.make_workload(1)
     om = oracle_mod.OracleMesh(m.xy, m.tri)
-    om.setup(oracle_mod.params(order=3))
+    om.setup(oracle_mod.params(order=order))
     oml = oracle_mod.OracleMesh(m.xy, m.tri)
-    oml.setup(oracle_mod.params(order=3, variant=1))
+    oml.setup(oracle_mod.params(order=order, variant=1))
     Ut, Ul = U.copy(), U.copy()
     for _ in range(w["steps"]):
         dt = om.dt(Ut, 0.4)
@@ -496,11 +500,28 @@ def _orders(e, n):
     return [math.log(e[i] / e[i + 1]) / math.log(n[i + 1] / n[i]) for i in range(len(e) - 1)]
 
 
+def _paper_finest_orders():
+    """Finest-pair (h = 1/80 -> 1/160) L2 orders of the printed accuracy
+    tables (Sec. 5.1, Tab. accuracy_order_3 .. accuracy_order_6)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_accuracy_orders.txt"))
+            if l.strip() and not l.startswith("#")]
+    return {int(r[0]): float(r[6]) for r in rows if r[1] == "1/160"}
+
+
+# three mesh levels per order; orders 5 and 6 reach their asymptotic slope
+# on coarser meshes, which keeps the CPU suite short
+CONVERGENCE_LEVELS = {3: [16, 32, 64], 4: [16, 32, 64], 5: [16, 24, 32], 6: [16, 24, 32]}
+
+
 @pytest.mark.parametrize("order", [3, 4, 5, 6])
 def test_convergence_order_entropy_wave(oracle_mod, order):
     # exact Euler solution rho = 1 + 0.2 sin(2 pi (x + y - 2t)), u = v = p = 1
+    # on three jittered meshes: the L2 slope between the two finest meshes is
+    # the design order to within the spread of the paper's own tables (its
+    # finest-pair slopes for advection on its meshes, Sec. 5.1: 3.01, 3.83,
+    # 5.01, 5.90), and it does not fall from the coarser pair
     T = 0.05
-    ns = [16, 32]
+    ns = CONVERGENCE_LEVELS[order]
     linf, l2 = [], []
     for n in ns:
         m, om = mesh_and_oracle(oracle_mod, n, 7, order)
@@ -512,9 +533,12 @@ def test_convergence_order_entropy_wave(oracle_mod, order):
         e = U[:, 0] - inputs.smooth_wave(m, t=T)[:, 0]
         linf.append(np.abs(e).max())
         l2.append(math.sqrt((area * e * e).sum()))
-    o_inf, o_2 = _orders(linf, ns)[0], _orders(l2, ns)[0]
-    assert o_2 > order - 0.6, (linf, l2)
-    assert o_inf > order - 1.0, (linf, l2)
+    o2 = [math.log(l2[i] / l2[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(2)]
+    oi = [math.log(linf[i] / linf[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(2)]
+    paper = _paper_finest_orders()[order]
+    assert abs(o2[1] - paper) <= 0.3, (o2, paper, l2)
+    assert o2[1] >= o2[0] - 0.05, (o2, l2)
+    assert oi[1] > order - 1.0, (oi, linf)
 
 
 # --------------------------------------------------------------------------
@@ -1166,3 +1190,71 @@ def test_box_vjp_dot_product_and_differences(oracle_mod, order, kinds):
     wb = np.zeros_like(w)
     wb[bcells] = w[bcells]
     assert abs((om.vjp(U, flags, wb) * v).sum()) > 1e-3 * abs((JTw * v).sum())
+
+
+# --------------------------------------------------------------------------
+# near-tie masks and the adjoint's comparison scale (the test bars)
+# --------------------------------------------------------------------------
+def test_tie_mask_marks_exactly_the_near_ties(oracle_mod):
+    # Sec. 3.3 cutoff: put C_T on one cell's chi_K; the mask marks that
+    # (cell, variable) and only selections whose chi lie in the band
+    m = inputs.jittered_periodic_mesh(12, 33)
+    U = inputs.random_lines(m)
+    om0 = oracle_mod.OracleMesh(m.xy, m.tri)
+    om0.setup(oracle_mod.params(order=4, fallback=1))
+    _, _, beta, _ = om0.reconstruct_cells(U, np.arange(m.n_cell))
+    g = 1.0 / (beta + 1e-12) ** 6
+    chiK = g[..., 3] / g.sum(-1)
+    cand = np.argwhere((chiK > 1e-3) & (chiK < 0.2))
+    cell, var = (int(x) for x in cand[len(cand) // 3])
+    ct = float(chiK[cell, var])
+    om = oracle_mod.OracleMesh(m.xy, m.tri)
+    om.setup(oracle_mod.params(order=4, fallback=1, ct=ct))
+    res = om.residual(U)
+    mask = res["diag"]["tie_mask"]
+    assert (mask[cell] >> (4 * var)) & 0xF == 0xF
+    # every marked nibble has a chi (step one, or step two when it ran) in
+    # the band, and every nibble is 0 or 0xF
+    chi2 = g[..., :3] / g[..., :3].sum(-1, keepdims=True)
+    band = lambda x: np.abs(x / ct - 1.0) <= 1e-10 * (1 + 1e-6)
+    for i, v in zip(*np.nonzero(np.stack([(mask >> (4 * v)) & 0xF for v in range(4)], 1))):
+        step2 = chiK[i, v] < ct
+        assert band(chiK[i, v]) or (step2 and band(chi2[i, v]).any()), (i, v)
+    nib = np.stack([(mask >> (4 * v)) & 0xF for v in range(4)], 1)
+    assert set(np.unique(nib).tolist()) <= {0, 0xF}
+    assert (nib == 0xF).sum() <= res["diag"]["near_ties"]
+    # the RK step reports each stage's ties; the first stage's are these
+    r = om.rk_step(U, om.dt(U, 0.4))
+    np.testing.assert_array_equal(r["diag"]["tie_mask"][0], mask)
+    # frozen selection has no ties to report
+    assert not om.residual(U, frozen_flags=res["flags"])["diag"]["tie_mask"].any()
+
+
+@pytest.mark.parametrize("order", [3, 5])
+def test_vjp_scale_bounds_every_adjoint(oracle_mod, order):
+    # the comparison scale sums the magnitudes of the adjoint's terms, so it
+    # bounds the adjoint (triangle inequality), for the residual and for a
+    # step, on a periodic mesh and on a box with every kind of side
+    for box in (False, True):
+        if box:
+            m = inputs.jittered_box_mesh(12, 8, 41, 1.5, 1.0)
+            om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
+            v, _ = om.boundary_faces()
+            _, side = inputs.face_sides(m, v)
+            kind = np.array([3, 1, 2, 2], np.int32)[side]
+            om.set_boundary(kind, np.tile(inputs.conservative(1.1, 0.3, 0.1, 0.9), (len(v), 1)))
+        else:
+            m = inputs.jittered_periodic_mesh(10, 40 + order)
+            om = oracle_mod.OracleMesh(m.xy, m.tri)
+        om.setup(oracle_mod.params(order=order, fallback=1))
+        U = inputs.random_lines(m)
+        fl = om.residual(U)["flags"]
+        lam = np.random.default_rng(order).normal(size=U.shape)
+        ub, S = om.vjp(U, fl, lam), om.vjp_scale(U, fl, lam)
+        assert (np.abs(ub) <= S * (1 + 1e-12)).all()
+        assert np.allclose(om.vjp_scale(U, fl, -lam), S, rtol=0, atol=0)
+        dt = om.dt(U, 0.4)
+        base = om.rk_step(U, dt, want_stages=True)
+        li = om.vjp_rk_step(base["stages"], base["flags"], dt, lam)
+        Si = om.vjp_rk_step_scale(base["stages"], base["flags"], dt, lam)
+        assert (np.abs(li) <= Si * (1 + 1e-12)).all()
