@@ -36,17 +36,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes_reconstruct(order: int, nq: int) -> int:
-    """Bytes one cell must move through the reconstruction kernel per stage:
-    its least-squares operators (3 small 5x11 + large nu x nl, FP64), its
-    stencil indices (int32), its own state (read once), its face-point
-    states (written once) and its selection flags."""
+def algorithmic_bytes_stage(order: int) -> int:
+    """Bytes one cell must move per RK stage, the fused minimum of the
+    method: its least-squares operators (3 small 5 x 11 + the large
+    nu x nl, FP64), its stencil indices (33 + nl int32), its state, U^n and
+    U^(k+1) (32 B each), and its share of the face geometry (1.5 faces x
+    (normal, |A|, two cell ids) + its face list and |V|: 68 B).  Stencil
+    gathers served from cache and intermediates are not counted: 2,100 /
+    3,060 / 4,980 / 8,340 B at orders 3-6."""
     r = order - 1
     nu = (r + 1) * (r + 2) // 2 - 1
     nl = (r + 1) * (r + 2) - 1
     ops = 8 * (3 * 5 * 11 + nu * nl)
     idx = 4 * (33 + nl)
-    return ops + idx + 32 + 3 * nq * 32 + 2
+    return ops + idx + 3 * 32 + 68
 
 
 def traffic_from_profiles(workload: str):
@@ -303,11 +306,12 @@ def dmr_timing(torch, teno, inputs, steps=10, warmup=2):
     return out
 
 
-def batch_timing(torch, teno, inputs, steps=10):
+def batch_timing(torch, teno, inputs, steps=100):
     """Batched workload: 64 seeded jittered periodic meshes, N ~ U{32..316},
     order ~ U{3..6}, random-line states; one step = per-mesh dt + one
-    SSP-RK3 step of every mesh.  Autotuned batched schedule against the same
-    meshes stepped one solver at a time."""
+    SSP-RK3 step of every mesh (one replay of the captured step graph).
+    All 100 steps of the workload are timed, for the autotuned batched
+    schedule and for the same meshes stepped one solver at a time."""
     from paper_2105_02127_amd.batch import Batch, autotune
     specs = inputs.batch_specs()
     solvers, U0 = [], []
@@ -325,17 +329,22 @@ def batch_timing(torch, teno, inputs, steps=10):
     b = Batch(solvers)
     dt = b.max_dt(U0, 0.4)
     best, timings = autotune(b, U0, dt, steps=3)
+    tuned = b.stats                 # the tuned schedule's graph is captured below
     U = [u.clone() for u in U0]
     for _ in range(2):
         b.max_dt(U, 0.4, dt)
         b.rk_step(U, dt)
     torch.cuda.synchronize()
+    before = b.stats
     t0 = time.perf_counter()
     for _ in range(steps):
         b.max_dt(U, 0.4, dt)
         b.rk_step(U, dt)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    after = b.stats
+    timed = {k: after[k] - before[k] for k in after}
+    finite = all(bool(torch.isfinite(u).all().item()) for u in U)
     # the same meshes, one solver at a time
     U = [u.clone() for u in U0]
     dts = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in solvers]
@@ -357,7 +366,12 @@ def batch_timing(torch, teno, inputs, steps=10):
             "ms_per_step": t_batch * 1e3 / steps,
             "single_mesh_sequential_value": cells * 3 * steps / t_seq,
             "batched_over_sequential": t_seq / t_batch,
-            "tuning": best, "setup_s": t_setup}
+            "tuning": best, "setup_s": t_setup,
+            "graph": {"captures_of_tuned_schedule": after["captures"] - tuned["captures"],
+                      "captures_in_timed_steps": timed["captures"],
+                      "replays_in_timed_steps": timed["replays"],
+                      "descriptor_writes_in_timed_steps": timed["descriptor_writes"]},
+            "finite": finite}
 
 
 def main():
@@ -407,11 +421,12 @@ def main():
     info = lm.info()
     Ud = torch.as_tensor(U0[lm.perm], device="cuda")
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
 
+    # a step = one SSP-RK3 step whose last stage also forms the next step's
+    # CFL dt from the states it writes (teno_rk_step_dt); the first step's
+    # dt comes from teno_max_dt
     def step():
-        sv.max_dt(Ud, 0.4, dt)
-        sv.rk_step(Ud, dt)
+        sv.rk_step_dt(Ud, dt, 0.4)
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
@@ -421,6 +436,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    sv.max_dt(Ud, 0.4, dt)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -453,8 +469,9 @@ def main():
     k1_ms = prof.ms["reconstruct"] / max(1, prof.launches["reconstruct"])
     per_launch = {k: brk.ms[k] / brk.launches[k] for k in ("reconstruct", "flux_update", "dt")
                   if brk.launches[k]}
-    bytes_k1 = algorithmic_bytes_reconstruct(order, nq) * n_cell
-    achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9 if k1_ms > 0 else None
+    bytes_stage = algorithmic_bytes_stage(order) * n_cell
+    achieved = bytes_stage / (k1_ms * 1e-3) / 1e9 if k1_ms > 0 else None
+    step_gbs = 3 * bytes_stage / (elapsed / args.steps) / 1e9
     traffic = traffic_from_profiles(w["name"])
     out = {
         "metric": METRIC if order == 5 else f"cell-updates/s per RK stage ({order}th-order, Euler)",
@@ -472,13 +489,23 @@ def main():
         "config": {"workload": w["name"], "n_cell": n_cell, "order": order, "n_quad": nq,
                    "ic": w["ic"], "seed": w["seed"], "cfl": 0.4,
                    "positivity_fallback": bool(args.fallback),
-                   "stage": "reconstruct + HLL flux + gather + RK update; dt once per step"},
+                   "nonphysical_cells_in_timed_stages": int(diag["nonphysical"]),
+                   "fallback_cells_in_timed_stages": int(diag["fallbacks"]),
+                   "note": ("the random-line states are not physical everywhere at the seams of "
+                            "the lines: the first-order fallback (not in the paper) replaces the "
+                            "face states of the cells counted above, after their full "
+                            "reconstruction") if diag["fallbacks"] else None,
+                   "stage": "reconstruct + HLL flux + gather + RK update; dt once per step, "
+                            "formed by the last stage's update"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic,
                      "kernel": "k_reconstruct",
-                     "algorithmic_bytes_per_launch": bytes_k1,
-                     "avg_launch_ms": k1_ms},
+                     "algorithmic_bytes_per_launch": bytes_stage,
+                     "algorithmic_bytes_per_cell": algorithmic_bytes_stage(order),
+                     "avg_launch_ms": k1_ms,
+                     "whole_step_gbs": step_gbs,
+                     "whole_step_frac": step_gbs / HBM_PEAK_GBS},
         "kernels_ms_per_launch": per_launch,
         "diagnostics": diag,
         "setup_s": t_setup,

@@ -213,6 +213,15 @@ int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk,
 int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flags3,
                  int32_t frozen, double* stages, double* face_states3, void* stream);
 
+/* One SSP-RK3 step in place on U (as teno_rk_step, unfrozen) that also
+ * leaves the next step's constant-CFL dt (as teno_max_dt of the new U, bit
+ * for bit) in dt_dev: the last stage's update kernel forms it from the
+ * states it writes, so a loop of steps needs teno_max_dt only before its
+ * first step.  dt_dev is the step's dt on entry and the next one on return;
+ * flags3 nullable (out). */
+int teno_rk_step_dt(teno_solver* s, double* U, double* dt_dev, double cfl, uint16_t* flags3,
+                    void* stream);
+
 /* Adjoint of the residual with the selection frozen to `flags`:
  * U_bar = (dR/dU)^T lam.  The reconstruction is linear in U for fixed
  * selection, so this is exact wherever the HLL flux is differentiable.  On
@@ -277,15 +286,33 @@ int teno_batch_create(teno_solver* const* solvers, int32_t n, teno_batch** out);
 int teno_batch_set_tuning(teno_batch* b, const teno_batch_tuning* t);
 int teno_batch_get_tuning(const teno_batch* b, teno_batch_tuning* t);
 
-/* dt_dev[m] = CFL step of mesh m from U[m] (device double[n]); two launches. */
+/* dt_dev[m] = CFL step of mesh m from U[m] (device double[n]); two launches.
+ * Leaves a captured step graph in place. */
 int teno_batch_max_dt(teno_batch* b, double* const* U, double cfl, double* dt_dev, void* stream);
 
 /* One SSP-RK3 step of every mesh, in place on U[m] (device state of mesh m,
- * internal order), with step dt_dev[m].  With use_graph the first call (and
- * any call with different pointers or tuning) captures the step as a HIP
- * graph; later calls replay it.  U (host array of n device pointers) and
- * dt_dev are read at capture time. */
+ * internal order), with step dt_dev[m].  The kernels take every pointer from
+ * per-mesh device descriptors, which teno_batch_max_dt and teno_batch_rk_step
+ * rewrite (a host-to-device copy and a wait on the stream) only when U,
+ * dt_dev or the flag buffers differ from the last call.  With use_graph the
+ * first call after teno_batch_create or teno_batch_set_tuning captures the
+ * step as a HIP graph and every call replays it; a loop over the same
+ * buffers makes no host wait per step. */
 int teno_batch_rk_step(teno_batch* b, double* const* U, const double* dt_dev, void* stream);
+
+/* Stage flags of the batched steps (Sec. 3.3 selection, encoded as for
+ * teno_rk_step): flags3[m] is a device uint16_t[3][n_cell of mesh m] that
+ * every later step overwrites with its three stages' flags; flags3 = NULL
+ * stops writing them.  Host array of n pointers, copied. */
+int teno_batch_set_flags(teno_batch* b, uint16_t* const* flags3);
+
+/* Counters of the batch since teno_batch_create. */
+typedef struct teno_batch_stats {
+  int64_t captures;           /* step graphs captured and instantiated        */
+  int64_t replays;            /* graph launches                               */
+  int64_t descriptor_writes;  /* descriptor uploads (each waits on the stream) */
+} teno_batch_stats;
+int teno_batch_get_stats(const teno_batch* b, teno_batch_stats* out);
 
 void teno_batch_destroy(teno_batch* b);
 

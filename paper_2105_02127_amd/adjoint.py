@@ -5,7 +5,8 @@ values of the forward pass.  For fixed selection the reconstruction is linear
 in the cell averages, so the step map is differentiable wherever the HLL flux
 is, and its vector-Jacobian product is what `teno_vjp_rk_step` computes on the
 device (the HLL flux differentiated in reverse mode, the reconstruction
-transposed into per-tile sums and a reverse-stencil gather, no atomics).
+transposed into per-tile sums formed in a fixed order and a reverse-stencil
+gather; no floating-point atomics, so reruns are bit-identical).
 
 Memory: U is checkpointed every `checkpoint_every` steps; the backward pass
 recomputes one segment at a time (its stage states, flags and, unless

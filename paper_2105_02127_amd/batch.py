@@ -72,6 +72,27 @@ class Batch:
             self.h, ptrs, float(cfl), C.c_void_p(dt.data_ptr()), st)))
         return dt
 
+    def set_flags(self, flags3):
+        """Per-mesh int16 tensors [3, n_cell] that later steps fill with their
+        stages' selection flags (uint16 bit patterns); None stops it."""
+        if flags3 is None:
+            teno._check(teno.load().teno_batch_set_flags(self.h, None))
+            self._flags = None
+            return
+        if len(flags3) != len(self.solvers):
+            raise teno.TenoError("one flag tensor per mesh")
+        for f, s in zip(flags3, self.solvers):
+            teno._ptr(f, (3, s.n_cell), torch.int16, "flags3")
+        self._flags = list(flags3)       # keeps the buffers alive
+        arr = (_vp * len(flags3))(*[f.data_ptr() for f in flags3])
+        teno._check(teno.load().teno_batch_set_flags(self.h, arr))
+
+    @property
+    def stats(self) -> dict:
+        st = teno.BatchStats()
+        teno._check(teno.load().teno_batch_get_stats(self.h, C.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in teno.BatchStats._fields_}
+
     def rk_step(self, U, dt):
         if dt.dtype != torch.float64 or dt.numel() != len(U) or not dt.is_contiguous():
             raise teno.TenoError("dt must be a contiguous float64 tensor with one entry per mesh")
@@ -88,9 +109,12 @@ CANDIDATES = [dict(order_mode=om, waves_per_cu=w, item_order=io, use_graph=1)
               for om, w, io in itertools.product((0, 1), (0, 4, 8, 16), (0, 1))]
 
 
-def autotune(batch: Batch, U, dt, steps: int = 3, cache: str | None = None, verbose=False):
+def autotune(batch: Batch, U, dt, steps: int = 3, cache: str | None = None, verbose=False,
+             cfl: float | None = 0.4):
     """Times every candidate schedule for `steps` batch steps (on scratch
-    copies of U) and applies the fastest; returns (best, timings)."""
+    copies of U) and applies the fastest; returns (best, timings).  With a
+    cfl each timed step is what a simulation loop runs: the per-mesh dt from
+    the current states, then the SSP-RK3 step (graph replay)."""
     key = batch.signature()
     if cache and os.path.exists(cache):
         try:
@@ -102,15 +126,21 @@ def autotune(batch: Batch, U, dt, steps: int = 3, cache: str | None = None, verb
             return known[key], {}
     work = [u.clone() for u in U]
     timings = {}
+
+    def step():
+        if cfl is not None:
+            batch.max_dt(work, cfl, dt)
+        batch.rk_step(work, dt)
+
     for cand in CANDIDATES:
         batch.set_tuning(**cand)
-        batch.rk_step(work, dt)                   # capture + warm-up
+        step()                                    # capture + warm-up
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            batch.rk_step(work, dt)
+            step()
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps

@@ -38,6 +38,7 @@ Dims dims_for(int order, int nq_req);
 // Largest number of distinct stencil members a 16-cell tile may have (their
 // states are staged in LDS, 32 bytes each).
 constexpr int kMaxTileMembers = 384;
+static_assert(kMaxTileMembers <= 512, "member slots take 9 bits of the adjoint's slot word");
 
 constexpr int kSmallRows = 11;
 constexpr int kSmallCoef = 5;
@@ -90,6 +91,11 @@ struct Mesh {
   std::vector<int32_t> cell_faces;  // [n_pad][4]: sorted face of local edges 0..2;
                                     //   bit e of [3] set when the cell is that face's L
   std::vector<double> vol;          // [n_pad] |V| (1 for padding cells)
+  // adjoint accumulation order: aslot[tile][rows4][16][4] = slot | round << 9,
+  // where round = how many earlier cells of the tile name the same member
+  // in that row; tround[tile] = the tile's largest round plus one
+  std::vector<uint16_t> aslot;
+  std::vector<int32_t> tround;
   // reverse member lists (adjoint gather): the tile member slots naming cell j
   std::vector<int32_t> rev_ptr; // [n_cell + 1]
   std::vector<int32_t> rev_ent; // tile * ustride + slot, by tile

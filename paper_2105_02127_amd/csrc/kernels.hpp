@@ -1054,7 +1054,7 @@ struct CellUpdateArgs {
 };
 
 template <bool RK>
-__device__ __forceinline__ void cell_update(const CellUpdateArgs& a, int t) {
+__device__ __forceinline__ void cell_update(const CellUpdateArgs& a, int t, double* kept = nullptr) {
   const int4 cf = a.cfaces[t];
   const double2* ph = reinterpret_cast<const double2*>(a.phi);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1077,7 +1077,11 @@ __device__ __forceinline__ void cell_update(const CellUpdateArgs& a, int t) {
     const double* un = a.Un + (size_t)t * 4;
     const double* uk = a.Uk + (size_t)t * 4;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) o[c] = a.ca * un[c] + a.cb * uk[c] + a.cc * (dt * R[c]);
+    for (int c = 0; c < 4; ++c) {
+      const double x = a.ca * un[c] + a.cb * uk[c] + a.cc * (dt * R[c]);
+      o[c] = x;
+      if (kept) kept[c] = x;
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) o[c] = R[c];
@@ -1107,10 +1111,9 @@ __device__ __forceinline__ double block_min(double x, double* sh) {
   return sh[0];
 }
 
-// |V_i| / sum_j |A_ij| (|u_i . n_ij| + c_i) from the cell average of cell t.
-__device__ __forceinline__ double cell_dt_limit(const double* __restrict__ U,
-                                                const double* __restrict__ geo, int t, double g) {
-  const double* u = U + (size_t)t * 4;
+// |V_i| / sum_j |A_ij| (|u_i . n_ij| + c_i) from the cell average u of cell t.
+__device__ __forceinline__ double dt_limit_of(const double* u, const double* __restrict__ geo,
+                                              int t, double g) {
   const double* gg = geo + (size_t)t * 10;
   const double vx = u[1] / u[0], vy = u[2] / u[0];
   const double p = (g - 1.0) * (u[3] - 0.5 * u[0] * (vx * vx + vy * vy));
@@ -1122,6 +1125,34 @@ __device__ __forceinline__ double cell_dt_limit(const double* __restrict__ U,
     den = den + gg[3 * e + 2] * (fabs(un) + c);
   }
   return gg[9] / den;
+}
+
+__device__ __forceinline__ double cell_dt_limit(const double* __restrict__ U,
+                                                const double* __restrict__ geo, int t, double g) {
+  return dt_limit_of(U + (size_t)t * 4, geo, t, g);
+}
+
+// The last stage's gather and update, fused with the first half of the
+// constant-CFL step of the state it writes: each block's minimum of
+// |V_i| / sum_j |A_ij| (|u_i . n_ij| + c_i) over its new cell averages, from
+// the values in registers and with k_dt_partial's arithmetic, so that
+// k_dt_final over these minima gives teno_max_dt of the new state bit for
+// bit.  (The minima are reduced by a second launch, not by the last block
+// to finish: on this multi-die GPU the device-scope fence that would order
+// each block's minimum before its count writes back the block's whole L2.)
+__global__ __launch_bounds__(256) void k_cell_update_dt(CellUpdateArgs a,
+                                                        const double* __restrict__ geo, double g,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int t = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  double lim = INFINITY;
+  if (t < a.n_cell) {
+    double u[4];
+    cell_update<true>(a, t, u);
+    lim = dt_limit_of(u, geo, t, g);
+  }
+  const double m = block_min(lim, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
 __global__ __launch_bounds__(256) void k_dt_partial(const double* __restrict__ U,
@@ -1253,14 +1284,19 @@ __global__ __launch_bounds__(256) void k_adj_boundary(AdjFaceArgs a, const int* 
 // Phase 2 (one wavefront per tile, one lane per (cell, variable)):
 // transpose of the reconstruction.  The adjoint of each stencil difference
 // d_s = U_s - U_0 goes to the tile's member slot of U_s, summed in LDS (one
-// accumulator per distinct member and variable, added with LDS atomics),
-// and the tile's sums are written once to tbar; the cell's own part (the
-// -U_0 of its differences and its face points) goes to own[n][4].
+// accumulator per distinct member and variable) in a fixed order: rows in
+// program order, and within a row the cells that name the same member in
+// rounds, in cell order (set-up assigns the rounds), so that no LDS
+// instruction has two lanes on one address and every sum is formed in the
+// same order on every run.  The tile's sums are written once to tbar; the
+// cell's own part (the -U_0 of its differences and its face points) goes to
+// own[n][4].
 struct AdjReconArgs {
   const double* __restrict__ fpbar;
   const uint16_t* __restrict__ flags;
   const double2* __restrict__ M;
-  const int4* __restrict__ slot;  // [n_tiles][rows4][16][4] uint16 member slots
+  const int4* __restrict__ aslot;   // [n_tiles][rows4][16][4] uint16: slot | round << 9
+  const int* __restrict__ tround;   // [n_tiles] rounds of the tile (largest round + 1)
   double* __restrict__ tbar;      // [n_tiles][ustride][4]
   double* __restrict__ own;       // [n_pad][4]
   int ustride;
@@ -1274,7 +1310,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   constexpr int NP = 3 * NQ;
   extern __shared__ double lds_acc[];  // 4 wavefronts x ustride x 4
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  const int tile = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
   double* acc = lds_acc + (size_t)wave * a.ustride * 4;
   for (int i = lane; i < 4 * a.ustride; i += 64) acc[i] = 0.0;
@@ -1300,8 +1336,20 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
       reinterpret_cast<const double*>(a.M + (size_t)tile * (O::JP / 2) * kTile + c);
   auto entry = [&](int j) { return mp[(size_t)(j >> 1) * (2 * kTile) + (j & 1)]; };
   const uint16_t* __restrict__ sl =
-      reinterpret_cast<const uint16_t*>(a.slot + (size_t)tile * slot_int4(O::ROWS4));
-  auto slot_of = [&](int r) { return (int)sl[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)]; };
+      reinterpret_cast<const uint16_t*>(a.aslot + (size_t)tile * slot_int4(O::ROWS4));
+  const int rounds = a.tround[tile];  // >= 1, the same for the whole wavefront
+  // row r's difference adjoint d into its member's accumulator, in its round
+  // (the first round unconditionally, so the slot word is loaded with the
+  // row's operator entries rather than after them)
+  auto add_row = [&](int r, double d) {
+    const int w = sl[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
+    double* dst = &acc[(w & 511) * 4 + v];
+    const int mine = w >> 9;
+    int q = 0;
+    do {
+      if (mine == q) atomicAdd(dst, d);
+    } while (++q < rounds);
+  };
   const bool keepK = nib & 8u;
   const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
   double dsum = 0.0;
@@ -1318,7 +1366,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
         for (int l = 0; l < 5; ++l) d = fma(entry(k * O::SBLK + entry_in_block(5, s, l)), ab[l], d);
         d *= wk;
         dsum += d;
-        atomicAdd(&acc[slot_of(small_row(k, s)) * 4 + v], d);
+        add_row(small_row(k, s), d);
       }
     }
   }
@@ -1332,7 +1380,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
         d = fma(entry(j), ab[l], d);
       }
       dsum += d;
-      atomicAdd(&acc[slot_of(large_row(s)) * 4 + v], d);
+      add_row(large_row(s), d);
     }
   }
   if (live) a.own[(size_t)cell * 4 + v] = gsum - dsum;

@@ -691,6 +691,8 @@ int mesh_setup(Mesh& m, const teno_params& p) {
     std::vector<std::vector<int32_t>> lists(m.n_tiles);
     std::atomic<int> umax{1};
     m.slot.assign(m.idx.size(), 0);
+    m.aslot.assign(m.idx.size(), 0);
+    m.tround.assign(m.n_tiles, 1);
     parallel_for(m.n_tiles, p.n_threads, [&](int tile) {
       std::vector<int32_t>& u = lists[tile];
       for (int c = 0; c < kTile; ++c) {
@@ -711,6 +713,20 @@ int mesh_setup(Mesh& m, const teno_params& p) {
           m.slot[k] = (uint16_t)(std::lower_bound(u.begin(), u.end(), m.idx[k]) - u.begin());
         }
       }
+      // rounds of the adjoint's per-row additions: cells of the tile that
+      // name the same member in the same row add in cell order, one round
+      // each, so no two lanes of one LDS instruction hit the same address
+      int top = 1;
+      for (int r = 0; r < d.rows; ++r)
+        for (int c = 0; c < kTile && tile * kTile + c < nc; ++c) {
+          const int64_t k = packed_idx_index(m, tile * kTile + c, r);
+          int q = 0;
+          for (int c2 = 0; c2 < c; ++c2)
+            if (m.slot[packed_idx_index(m, tile * kTile + c2, r)] == m.slot[k]) ++q;
+          m.aslot[k] = (uint16_t)(m.slot[k] | q << 9);
+          top = std::max(top, q + 1);
+        }
+      m.tround[tile] = top;
     });
     if (umax.load() > kMaxTileMembers)
       return fail(TENO_ESTENCIL, "a 16-cell tile has " + std::to_string(umax.load()) +

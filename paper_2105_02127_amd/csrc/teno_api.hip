@@ -70,6 +70,8 @@ struct teno_solver {
   teno_params prm{};
   int n_cell = 0, n_pad = 0, n_tiles = 0;
   int4* slot = nullptr;     // member slots of each tile's stencil rows (uint16)
+  int4* aslot = nullptr;    // adjoint: member slot and accumulation round per row
+  int* tround = nullptr;    // adjoint: rounds per tile
   int* tmem = nullptr;      // distinct stencil members of each tile
   int ustride = 0;
   double2* M = nullptr;
@@ -233,9 +235,12 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   return rc;
 }
 
+// next_dt (nullable, last stage only): the update also forms the CFL step of
+// the state it produces (k_cell_update_dt, then k_dt_final) into *next_dt,
+// with cfl next_cfl.
 int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
                 const double* dt, double ca, double cb, double cc, bool rk, hipStream_t st,
-                const double* fp = nullptr) {
+                const double* fp = nullptr, double* next_dt = nullptr, double next_cfl = 0.0) {
   FaceFluxArgs f;
   f.fp = fp ? fp : s->fp;
   f.fcell = s->fcell;
@@ -267,7 +272,12 @@ int launch_flux(teno_solver* s, const double* Un, const double* Uk, double* out,
       if (s->n_bface > 0)
         hipLaunchKernelGGL((k_boundary_flux<decltype(NQ)::value>), dim3((s->n_bface + 255) / 256),
                            dim3(256), 0, st, f, (const int*)s->bface, s->n_bface);
-      if (rk)
+      if (rk && next_dt) {
+        hipLaunchKernelGGL(k_cell_update_dt, dim3(cblocks), dim3(256), 0, st, c,
+                           (const double*)s->geo, s->prm.gamma, s->dtpart);
+        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, st, (const double*)s->dtpart,
+                           cblocks, next_cfl, next_dt);
+      } else if (rk)
         hipLaunchKernelGGL((k_cell_update<true>), dim3(cblocks), dim3(256), 0, st, c);
       else
         hipLaunchKernelGGL((k_cell_update<false>), dim3(cblocks), dim3(256), 0, st, c);
@@ -316,7 +326,8 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   ra.fpbar = s->fpbar;
   ra.flags = flags;
   ra.M = s->M;
-  ra.slot = s->slot;
+  ra.aslot = s->aslot;
+  ra.tround = s->tround;
   ra.tbar = s->tbar;
   ra.ustride = s->ustride;
   ra.own = s->own;
@@ -532,6 +543,8 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
   };
   s->ustride = m.ustride;
   A(s->slot, m.slot.size() / 8);
+  A(s->aslot, m.aslot.size() / 8);
+  A(s->tround, m.tround.size());
   A(s->tmem, m.tmem.size());
   A(s->M, m.M.size() / 2);
   A(s->nbinfo, np);
@@ -569,6 +582,8 @@ int teno_solver_create(const teno_mesh* mesh, int32_t device, teno_solver** out)
     const void* src;
     size_t n;
   } ups[] = {{s->slot, m.slot.data(), m.slot.size() * sizeof(uint16_t)},
+             {s->aslot, m.aslot.data(), m.aslot.size() * sizeof(uint16_t)},
+             {s->tround, m.tround.data(), m.tround.size() * sizeof(int32_t)},
              {s->tmem, m.tmem.data(), m.tmem.size() * sizeof(int32_t)},
              {s->M, m.M.data(), m.M.size() * sizeof(double)},
              {s->nbinfo, m.nbinfo.data(), m.nbinfo.size() * sizeof(int32_t)},
@@ -654,13 +669,13 @@ int teno_max_dt(teno_solver* s, const double* U, double cfl, double* dt_dev, voi
   return launch_dt(s, U, cfl, dt_dev, (hipStream_t)stream);
 }
 
-
 static int stage_impl(teno_solver* s, int k, const double* Un, const double* Uk, double* Uk1,
                       const double* dt, uint16_t* flags, bool frozen, hipStream_t st,
-                      double* fp = nullptr) {
+                      double* fp = nullptr, double* next_dt = nullptr, double next_cfl = 0.0) {
   int rc = launch_reconstruct(s, Uk, flags, frozen, st, fp);
   if (rc) return rc;
-  return launch_flux(s, Un, Uk, Uk1, dt, kStageA[k], kStageB[k], kStageC[k], true, st, fp);
+  return launch_flux(s, Un, Uk, Uk1, dt, kStageA[k], kStageB[k], kStageC[k], true, st, fp,
+                     next_dt, next_cfl);
 }
 
 int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk, double* Uk1,
@@ -709,6 +724,22 @@ int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flag
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   }
   return stage_impl(s, 2, U, s->W2, U, dt_dev, fl(2), frozen != 0, st, fs(2));
+}
+
+int teno_rk_step_dt(teno_solver* s, double* U, double* dt_dev, double cfl, uint16_t* flags3,
+                    void* stream) {
+  if (int rc = check_solver(s)) return rc;
+  if (!U || !dt_dev) return fail(TENO_EARG, "null argument");
+  if (!(cfl > 0.0)) return fail(TENO_EARG, "cfl must be positive");
+  DeviceScope ds(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nfl = (size_t)s->n_cell * (s->prm.characteristic ? 3 : 1);
+  auto fl = [&](int k) { return flags3 ? flags3 + (size_t)k * nfl : nullptr; };
+  int rc = stage_impl(s, 0, U, U, s->W1, dt_dev, fl(0), false, st);
+  if (rc) return rc;
+  rc = stage_impl(s, 1, U, s->W1, s->W2, dt_dev, fl(1), false, st);
+  if (rc) return rc;
+  return stage_impl(s, 2, U, s->W2, U, dt_dev, fl(2), false, st, nullptr, dt_dev, cfl);
 }
 
 int teno_vjp_residual(teno_solver* s, const double* U, const uint16_t* flags, const double* lam,
@@ -840,12 +871,16 @@ struct teno_batch {
   };
   std::vector<RLaunch> rplan;
   int n_waves_f = 0, n_waves_c = 0, n_items_dt = 0, n_items_b = 0;
-  // graph
+  // graph of one step: its kernels read every pointer from the device
+  // descriptors, so it stays valid while only the descriptors change
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<double*> graph_U;
-  const double* graph_dt = nullptr;
-  hipStream_t graph_stream = nullptr;
+  // what the device descriptors were last written for
+  bool desc_valid = false;
+  std::vector<double*> desc_U;
+  const double* desc_dt = nullptr;
+  std::vector<uint16_t*> flags3;  // per mesh [3][n_cell] stage flags, or empty
+  teno_batch_stats stats{0, 0, 0};
   std::vector<void*> allocs;
 
   template <class T>
@@ -862,12 +897,12 @@ struct teno_batch {
     if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
-    graph_U.clear();
   }
   void free_plan() {
     for (void* q : allocs) (void)hipFree(q);
     allocs.clear();
     meshes = nullptr;
+    desc_valid = false;
   }
   ~teno_batch() {
     drop_graph();
@@ -1016,8 +1051,14 @@ int batch_plan(teno_batch* b) {
   return TENO_OK;
 }
 
-// Writes the per-mesh descriptors for state pointers U[m] and steps dt[m].
+// Makes the per-mesh descriptors describe state pointers U[m] and steps
+// dt[m].  They are rewritten (a host-to-device copy and a wait on the
+// stream) only when these pointers, the flag buffers or the plan changed
+// since the last write; a step loop over the same buffers writes them once.
 int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStream_t st) {
+  if (b->desc_valid && b->desc_dt == dt && (int)b->desc_U.size() == b->n &&
+      std::equal(U, U + b->n, b->desc_U.begin()))
+    return TENO_OK;
   std::vector<BatchMeshDev> h(b->n);
   for (int m = 0; m < b->n; ++m) {
     teno_solver* s = b->sv[m];
@@ -1042,6 +1083,7 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
       a.n_cell = s->n_cell;
       a.n_tiles = s->n_tiles;
       a.n_pad = s->n_pad;
+      a.flags = b->flags3.empty() ? nullptr : b->flags3[m] + (size_t)k * s->n_cell;
       a.frozen = 0;
       a.variant = s->prm.variant;
       a.fallback = s->prm.fallback;
@@ -1083,10 +1125,18 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
     d.bface = s->bface;
     d.n_bface = s->n_bface;
   }
+  // the host copy is freed on return, so the stream waits for the copy
   hipError_t e = hipMemcpyAsync(b->meshes, h.data(), h.size() * sizeof(BatchMeshDev),
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+  if (e != hipSuccess) {
+    b->desc_valid = false;
+    return hip_fail(e, "batch descriptors");
+  }
+  b->desc_U.assign(U, U + b->n);
+  b->desc_dt = dt;
+  b->desc_valid = true;
+  b->stats.descriptor_writes++;
   return TENO_OK;
 }
 
@@ -1196,7 +1246,6 @@ int teno_batch_max_dt(teno_batch* b, double* const* U, double cfl, double* dt_de
     if (!U[m]) return fail(TENO_EARG, "null state pointer");
   DeviceScope ds(b->device);
   hipStream_t st = (hipStream_t)stream;
-  b->drop_graph();  // descriptors are rewritten below
   int rc = batch_descriptors(b, U, dt_dev, st);
   if (rc) return rc;
   hipLaunchKernelGGL(k_batch_dt_partial, dim3(b->n_items_dt), dim3(256), 0, st, b->meshes,
@@ -1214,34 +1263,50 @@ int teno_batch_rk_step(teno_batch* b, double* const* U, const double* dt_dev, vo
     if (!U[m]) return fail(TENO_EARG, "null state pointer");
   DeviceScope ds(b->device);
   hipStream_t st = (hipStream_t)stream;
-  bool same = b->exec && b->graph_dt == dt_dev && b->graph_stream == st &&
-              (int)b->graph_U.size() == b->n && std::equal(U, U + b->n, b->graph_U.begin());
-  if (!same) {
-    b->drop_graph();
-    int rc = batch_descriptors(b, U, dt_dev, st);
-    if (rc) return rc;
-    if (b->tune.use_graph) {
-      if (st == nullptr) return fail(TENO_EARG, "graph capture needs a non-default stream");
-      hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      batch_launch_step(b, st);
-      e = hipStreamEndCapture(st, &b->graph);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-      b->graph_U.assign(U, U + b->n);
-      b->graph_dt = dt_dev;
-      b->graph_stream = st;
+  int rc = batch_descriptors(b, U, dt_dev, st);
+  if (rc) return rc;
+  if (b->tune.use_graph && !b->exec) {
+    if (st == nullptr) return fail(TENO_EARG, "graph capture needs a non-default stream");
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    batch_launch_step(b, st);
+    e = hipStreamEndCapture(st, &b->graph);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      b->drop_graph();
+      return hip_fail(e, "hipGraphInstantiate");
     }
+    b->stats.captures++;
   }
   if (b->tune.use_graph) {
     hipError_t e = hipGraphLaunch(b->exec, st);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    b->stats.replays++;
   } else {
     batch_launch_step(b, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batch launch");
   }
+  return TENO_OK;
+}
+
+int teno_batch_set_flags(teno_batch* b, uint16_t* const* flags3) {
+  if (!b) return fail(TENO_EARG, "null argument");
+  if (flags3)
+    for (int m = 0; m < b->n; ++m)
+      if (!flags3[m]) return fail(TENO_EARG, "null flag pointer");
+  if (flags3)
+    b->flags3.assign(flags3, flags3 + b->n);
+  else
+    b->flags3.clear();
+  b->desc_valid = false;  // the next call writes them into the descriptors
+  return TENO_OK;
+}
+
+int teno_batch_get_stats(const teno_batch* b, teno_batch_stats* out) {
+  if (!b || !out) return fail(TENO_EARG, "null argument");
+  *out = b->stats;
   return TENO_OK;
 }
 
@@ -1252,3 +1317,4 @@ void teno_batch_destroy(teno_batch* b) {
 }
 
 }  // extern "C"
+

@@ -40,6 +40,11 @@ class BatchTuning(C.Structure):
                 ("item_order", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("captures", C.c_int64), ("replays", C.c_int64),
+                ("descriptor_writes", C.c_int64)]
+
+
 class Diag(C.Structure):
     _fields_ = [("nonphysical", C.c_int64), ("first_bad_cell", C.c_int64),
                 ("near_ties", C.c_int64), ("fallbacks", C.c_int64)]
@@ -68,6 +73,7 @@ SIGNATURES = {
     "teno_max_dt": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
     "teno_rk_stage": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "teno_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "teno_rk_step_dt": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp]),
     "teno_vjp_residual": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "teno_vjp_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "teno_diagnostics": (C.c_int, [_vp, C.POINTER(Diag), _i32, _vp]),
@@ -79,6 +85,8 @@ SIGNATURES = {
     "teno_batch_get_tuning": (C.c_int, [_vp, C.POINTER(BatchTuning)]),
     "teno_batch_max_dt": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, _vp, _vp]),
     "teno_batch_rk_step": (C.c_int, [_vp, C.POINTER(_vp), _vp, _vp]),
+    "teno_batch_set_flags": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "teno_batch_get_stats": (C.c_int, [_vp, C.POINTER(BatchStats)]),
     "teno_batch_destroy": (None, [_vp]),
 }
 
@@ -365,6 +373,13 @@ class Solver:
         _check(load().teno_rk_step(self.h, self._state(U, "U"), self._dt(dt),
                                    self._flags(flags3, 3, "flags3"), 1 if frozen else 0, st,
                                    self._face_states(face_states), _stream(stream)))
+        return U
+
+    def rk_step_dt(self, U, dt, cfl=0.4, flags3=None, stream=None):
+        """One SSP-RK3 step in place with dt; dt then holds the next step's
+        CFL step (teno_rk_step_dt)."""
+        _check(load().teno_rk_step_dt(self.h, self._state(U, "U"), self._dt(dt), float(cfl),
+                                      self._flags(flags3, 3, "flags3"), _stream(stream)))
         return U
 
     def vjp_residual(self, U, flags, lam, U_bar=None, stream=None):

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2105_02127_amd import inputs
+from parity_check import assert_adjoint
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +40,10 @@ def test_rollout_gradient_matches_oracle(oracle_mod, torch_cuda):
         recs.append((r["stages"], r["flags"], dt))
         U = r["U"]
     w = np.random.default_rng(5).normal(size=U.shape)
-    lam = w.copy()
+    lam, scale = w.copy(), np.abs(w)
     for st, fl, dt in reversed(recs):
         lam = om.vjp_rk_step(st, fl, dt, lam)
+        scale = om.vjp_rk_step_scale(st, fl, dt, scale)
     # GPU: same dt sequence replayed
     dts = torch.tensor([d for _, _, d in recs], dtype=torch.float64, device="cuda")
     U0d = torch.as_tensor(U0[perm], device="cuda").requires_grad_(True)
@@ -54,7 +56,7 @@ def test_rollout_gradient_matches_oracle(oracle_mod, torch_cuda):
     Ug[perm] = UT.detach().cpu().numpy()
     for v in range(4):
         assert np.abs(Ug[:, v] - U[:, v]).max() <= 1e-12 * np.abs(U[:, v]).max()
-        assert np.abs(g[:, v] - lam[:, v]).max() <= 1e-10 * np.abs(lam[:, v]).max(), v
+    assert_adjoint(g, lam, scale, what=f"rollout gradient, {steps} steps")
 
 
 def test_rollout_gradient_on_a_box_matches_oracle(oracle_mod, torch_cuda):
@@ -87,9 +89,10 @@ def test_rollout_gradient_on_a_box_matches_oracle(oracle_mod, torch_cuda):
         recs.append((r["stages"], r["flags"], dt))
         U = r["U"]
     w = np.random.default_rng(9).normal(size=U.shape)
-    lam = w.copy()
+    lam, scale = w.copy(), np.abs(w)
     for st, fl, dt in reversed(recs):
         lam = om.vjp_rk_step(st, fl, dt, lam)
+        scale = om.vjp_rk_step_scale(st, fl, dt, scale)
     dts = torch.tensor([d for _, _, d in recs], dtype=torch.float64, device="cuda")
     U0d = torch.as_tensor(U0[perm], device="cuda").requires_grad_(True)
     UT, _ = adjoint.rollout(sv, U0d, steps, checkpoint_every=K, dts=dts)
@@ -100,7 +103,7 @@ def test_rollout_gradient_on_a_box_matches_oracle(oracle_mod, torch_cuda):
     Ug[perm] = UT.detach().cpu().numpy()
     for v in range(4):
         assert np.abs(Ug[:, v] - U[:, v]).max() <= 1e-12 * np.abs(U[:, v]).max()
-        assert np.abs(g[:, v] - lam[:, v]).max() <= 1e-10 * np.abs(lam[:, v]).max(), v
+    assert_adjoint(g, lam, scale, what=f"box rollout gradient, {steps} steps")
 
 
 def test_keep_all_equals_checkpointed(torch_cuda):

@@ -1,10 +1,12 @@
 """Batched path: meshes of mixed size and order advanced together must give,
 mesh by mesh, exactly the single-mesh result (same kernels, deterministic),
-with every schedule option, eagerly and from graph replays."""
+with every schedule option, eagerly and from graph replays; and on meshes of
+the 64-mesh workload itself, the oracle's result."""
 import numpy as np
 import pytest
 
 from paper_2105_02127_amd import inputs
+from paper_2105_02127_amd.batch import CANDIDATES
 
 pytestmark = pytest.mark.gpu
 
@@ -109,3 +111,105 @@ def test_characteristic_meshes_are_not_batched(torch_cuda):
     s = teno.Solver(teno.Mesh(m.xy, m.tri).setup(order=4, characteristic=1))
     with pytest.raises(teno.TenoError):
         Batch([s])
+
+
+# --------------------------------------------------------------------------
+# the batched workload's own meshes against the oracle
+# --------------------------------------------------------------------------
+# (N, order, seed) taken from the 64-mesh workload (inputs.batch_specs): its
+# largest mesh (316^2 x 2 = 199,712 cells, order 6), the largest of orders 4
+# and 5, two of order 3 and its smallest mesh (N = 32)
+ORACLE_SPECS = [(316, 6, 5019), (311, 4, 5008), (309, 5, 5027), (279, 3, 5051), (74, 3, 5018),
+                (32, 5, 5016)]
+
+
+@pytest.fixture(scope="module")
+def oracle_batch(torch_cuda, oracle_mod):
+    """GPU solvers and initial states of ORACLE_SPECS, and per mesh the
+    oracle's dt and one SSP-RK3 step (state, stage flags, near-tie masks)."""
+    torch = torch_cuda
+    from paper_2105_02127_amd import teno
+    spec = {tuple(s) for s in inputs.batch_specs()}
+    assert all(s in spec for s in ORACLE_SPECS)
+    sv, U0, ref, perms = [], [], [], []
+    for n, p, seed in ORACLE_SPECS:
+        print(f"[batch oracle] N={n} order={p} seed={seed}", flush=True)
+        m = inputs.jittered_periodic_mesh(n, seed)
+        U = inputs.random_lines(m)
+        lm = teno.Mesh(m.xy, m.tri).setup(order=p, fallback=1)
+        sv.append(teno.Solver(lm))
+        perms.append(lm.perm)
+        U0.append(torch.as_tensor(U[lm.perm], device="cuda"))
+        om = oracle_mod.OracleMesh(m.xy, m.tri)
+        om.setup(oracle_mod.params(order=p, fallback=1))
+        dto = om.dt(U, 0.4)
+        r = om.rk_step(U, dto)
+        ref.append(dict(dt=dto, U=r["U"], flags=r["flags"], ties=r["diag"]["tie_mask"]))
+    return sv, U0, ref, perms
+
+
+SCHEDULES = ([dict(c) for c in CANDIDATES]
+             + [dict(order_mode=om, waves_per_cu=w, item_order=1, use_graph=0)
+                for om, w in ((0, 0), (1, 0), (1, 8))])
+
+
+def test_batch_matches_oracle_on_workload_meshes(torch_cuda, oracle_batch):
+    # every schedule (the autotuner's candidates, eager and replayed): one
+    # batched SSP-RK3 step with the oracle's dt per mesh, compared mesh by
+    # mesh with the oracle: states to 1e-12, flags of every stage exact away
+    # from near ties
+    from parity_check import assert_states, check_flags
+    torch = torch_cuda
+    from paper_2105_02127_amd.batch import Batch
+    sv, U0, ref, perms = oracle_batch
+    b = Batch(sv)
+    dt = torch.tensor([r["dt"] for r in ref], dtype=torch.float64, device="cuda")
+    flags = [s.empty_flags(3) for s in sv]
+    b.set_flags(flags)
+    for tuning in SCHEDULES:
+        print(f"[batch oracle] schedule {tuning}", flush=True)
+        b.set_tuning(**tuning)
+        work = [u.clone() for u in U0]
+        for f in flags:
+            f.fill_(0)
+        b.rk_step(work, dt)
+        torch.cuda.synchronize()
+        for k, (w, r, perm, f) in enumerate(zip(work, ref, perms, flags)):
+            got = np.empty_like(r["U"])
+            got[perm] = w.cpu().numpy()
+            assert_states(got, r["U"], what=f"mesh {k} {ORACLE_SPECS[k]} {tuning}")
+            gfl = np.empty((3, len(perm)), np.uint16)
+            gfl[:, perm] = f.cpu().numpy().view(np.uint16)
+            for st in range(3):
+                check_flags(gfl[st], r["flags"][st], r["ties"][st],
+                            what=f"mesh {k} stage {st} {tuning}")
+
+
+def test_batch_loop_captures_once_and_never_rewrites(torch_cuda, oracle_batch):
+    # a simulation loop (dt, then step, on the same buffers) captures its
+    # graph once and writes the descriptors once; replays match eager steps
+    torch = torch_cuda
+    from paper_2105_02127_amd.batch import Batch
+    sv, U0, _, _ = oracle_batch
+    small = [(s, u) for s, u in zip(sv, U0) if s.n_cell < 20000]
+    b = Batch([s for s, _ in small])
+    b.set_tuning(order_mode=1, waves_per_cu=0, item_order=1, use_graph=1)
+    work = [u.clone() for _, u in small]
+    dt = torch.empty(len(small), dtype=torch.float64, device="cuda")
+    s0 = b.stats
+    for _ in range(5):
+        b.max_dt(work, 0.4, dt)
+        b.rk_step(work, dt)
+    torch.cuda.synchronize()
+    st = b.stats
+    assert st["captures"] - s0["captures"] == 1
+    assert st["descriptor_writes"] - s0["descriptor_writes"] == 1
+    assert st["replays"] - s0["replays"] == 5
+    eager = [u.clone() for _, u in small]
+    for _ in range(5):
+        for (s, _), u in zip(small, eager):
+            d = s.max_dt(u, 0.4)
+            s.rk_step(u, d)
+    torch.cuda.synchronize()
+    for g, e in zip(work, eager):
+        assert torch.equal(g, e)
