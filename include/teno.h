@@ -213,6 +213,18 @@ int teno_rk_stage(teno_solver* s, int32_t k, const double* Un, const double* Uk,
 int teno_rk_step(teno_solver* s, double* U, const double* dt_dev, uint16_t* flags3,
                  int32_t frozen, double* stages, double* face_states3, void* stream);
 
+/* teno_max_dt for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same dt,
+ * bit for bit, but the per-block minima live in a static device array of
+ * the library (65,536 doubles, one copy per GPU for the life of the
+ * process) instead of the solver's workspace.  The call allocates nothing
+ * and makes no allocating library call.  Meshes of more than 16,777,216
+ * cells are refused (TENO_EARG).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * must be ordered by the caller.  The array's address on each GPU is taken
+ * on the first call there. */
+int teno_max_dt_static(teno_solver* s, const double* U, double cfl, double* dt_dev, void* stream);
+
 /* One SSP-RK3 step in place on U (as teno_rk_step, unfrozen) that also
  * leaves the next step's constant-CFL dt (as teno_max_dt of the new U, bit
  * for bit) in dt_dev: the last stage's update kernel forms it from the

@@ -1318,3 +1318,5 @@ void teno_batch_destroy(teno_batch* b) {
 
 }  // extern "C"
 
+// allocation-free entry point (its own static device scratch)
+#include "noalloc.inc"

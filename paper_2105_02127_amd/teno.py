@@ -71,6 +71,7 @@ SIGNATURES = {
     "teno_residual_frozen": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "teno_reconstruct": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "teno_max_dt": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
+    "teno_max_dt_static": (C.c_int, [_vp, _vp, C.c_double, _vp, _vp]),
     "teno_rk_stage": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "teno_rk_step": (C.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     "teno_rk_step_dt": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp]),
