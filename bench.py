@@ -306,6 +306,79 @@ def dmr_timing(torch, teno, inputs, steps=10, warmup=2):
     return out
 
 
+def algorithmic_bytes_stage3(order: int) -> int:
+    """Tetrahedra: bytes one cell must move per RK stage, the fused minimum
+    as for triangles: its least-squares operators (4 small 9 x 19 + the
+    large nu x nl, FP64), stencil indices (76 + nl int32), its state, U^n and
+    U^(k+1) (40 B each) and its share of the face geometry (2 faces x
+    (normal, |A|, two cell ids) + its face list and |V|: 104 B): 7,444 /
+    12,084 / 25,044 / 55,284 B at orders 3-6."""
+    r = order - 1
+    nu = (r + 1) * (r + 2) * (r + 3) // 6 - 1
+    nl = 2 * (nu + 1) - 1
+    ops = 8 * (4 * 9 * 19 + nu * nl)
+    idx = 4 * (4 * 19 + nl)
+    return ops + idx + 3 * 40 + 104
+
+
+def tet_timing(torch, steps=10, warmup=2):
+    """Tetrahedra (the method in three reference coordinates): TENO3-6 on the
+    jittered periodic 32^3 x 6 = 196,608-cell cube with random planes, and
+    the paper's 3D explosion (Sec. 5.9, edge h ~ 1/30) with TENO4 on
+    [-1, 1]^3 split into 60^3 x 6 = 1,296,000 tetrahedra with transmissive
+    sides; per-stage throughput and the roofline of the reconstruction."""
+    from paper_2105_02127_amd import inputs3, teno3
+    out = {"schemes": {}}
+    for name, wl, order in (("TENO3_planes_N32", "teno4_planes_N32", 3),
+                            ("TENO4_planes_N32", "teno4_planes_N32", 4),
+                            ("TENO5_planes_N32", "teno4_planes_N32", 5),
+                            ("TENO6_planes_N32", "teno4_planes_N32", 6),
+                            ("TENO4_explosion3_N60", "explosion3_N60", 4)):
+        w, mesh, U0 = inputs3.make_workload3(wl)
+        t0 = time.perf_counter()
+        lm = teno3.TetMesh(mesh.xyz, mesh.tet, period=mesh.period).setup(
+            order=order, fallback=w["fallback"])
+        t_setup = time.perf_counter() - t0
+        sv = teno3.TetSolver(lm)
+        U = torch.as_tensor(U0[lm.perm], device="cuda")
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            sv.max_dt(U, 0.4, dt)
+            sv.rk_step(U, dt)
+        torch.cuda.synchronize()
+        sv.diagnostics(reset=True)
+        sv.profile_read(reset=True)
+        sv.profile_enable(kinds=("reconstruct",))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sv.max_dt(U, 0.4, dt)
+            sv.rk_step(U, dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sv.profile_enable(kinds=())
+        prof = sv.profile_read(reset=True)
+        diag = sv.diagnostics(reset=True)
+        rec_ms = prof.ms["reconstruct"] / max(1, prof.launches["reconstruct"])
+        bytes_stage = algorithmic_bytes_stage3(order) * mesh.n_cell
+        achieved = bytes_stage / (rec_ms * 1e-3) / 1e9 if rec_ms > 0 else None
+        step_gbs = 3 * bytes_stage / (el / steps) / 1e9
+        out["schemes"][name] = {
+            "workload": wl, "n_cell": mesh.n_cell, "order": order, "steps": steps,
+            "value": mesh.n_cell * 3 * steps / el, "unit": "cell-updates/s",
+            "ms_per_step": el * 1e3 / steps, "setup_s": t_setup,
+            "recon_avg_launch_ms": rec_ms,
+            "algorithmic_bytes_per_cell": algorithmic_bytes_stage3(order),
+            "recon_achieved_gbs": achieved,
+            "recon_frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "whole_step_gbs": step_gbs, "whole_step_frac": step_gbs / HBM_PEAK_GBS,
+            "fallback_cells": int(diag["fallbacks"]),
+            "finite": bool(torch.isfinite(U).all().item())}
+        print(f"[tet] {name}: {out['schemes'][name]['value']:.3e} cell-updates/s, "
+              f"recon {rec_ms:.3f} ms, setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+        del sv, lm, U
+    return out
+
+
 def batch_timing(torch, teno, inputs, steps=100):
     """Batched workload: 64 seeded jittered periodic meshes, N ~ U{32..316},
     order ~ U{3..6}, random-line states; one step = per-mesh dt + one
@@ -391,7 +464,10 @@ def main():
                     help="skip the stream-triad bandwidth measured for context")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-khi", action="store_true", help="skip the KHI TENO3-6 timings")
+    ap.add_argument("--khi-steps", type=int, default=10, help="timed steps per KHI/DMR scheme")
+    ap.add_argument("--khi-warmup", type=int, default=2, help="warm-up steps per KHI/DMR scheme")
     ap.add_argument("--no-dmr", action="store_true", help="skip the DMR TENO3-6 timings")
+    ap.add_argument("--no-tet", action="store_true", help="skip the tetrahedral timings")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-launch HIP events (no roofline figures)")
     ap.add_argument("--breakdown-steps", type=int, default=5,
@@ -519,9 +595,11 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_timing(torch, teno, inputs)
     if not args.no_khi:
-        out["khi"] = khi_timing(torch, teno, inputs)
+        out["khi"] = khi_timing(torch, teno, inputs, args.khi_steps, args.khi_warmup)
     if not args.no_dmr:
-        out["dmr"] = dmr_timing(torch, teno, inputs)
+        out["dmr"] = dmr_timing(torch, teno, inputs, args.khi_steps, args.khi_warmup)
+    if not args.no_tet:
+        out["tetrahedra"] = tet_timing(torch, args.khi_steps, args.khi_warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, U0, order, args.fallback, args.cpu_steps,
                                            single=not args.no_cpu_single)

@@ -36,15 +36,21 @@ def build(verbose: bool = False, resource_usage: bool = False, lib: str = LIB,
     # layout macros must reach both the host set-up and the kernels
     layout = [f for f in extra_hip if f.startswith("-DTENO_TILE")]
     setup_o = os.path.join(BUILD, "setup.o")
+    setup3_o = os.path.join(BUILD, "setup3.o")
     api_o = os.path.join(BUILD, "teno_api.o")
+    api3_o = os.path.join(BUILD, "teno3_api.o")
     _run(["g++", *HOST_FLAGS, *layout, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o],
          verbose)
+    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup3.cpp"), "-o", setup3_o], verbose)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
     _run(["hipcc", *HIP_FLAGS, *extra_hip, *extra, "-c", os.path.join(CSRC, "teno_api.hip"), "-o",
           api_o], verbose)
+    # the tetrahedral path: a translation unit of its own
+    _run(["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, "teno3_api.hip"), "-o", api3_o],
+         verbose)
     tmp = lib + ".tmp"
     _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
-          setup_o, api_o, "-pthread",
+          setup_o, setup3_o, api_o, api3_o, "-pthread",
           "-o", tmp], verbose)
     os.replace(tmp, lib)
     return lib

@@ -1,0 +1,455 @@
+// HIP kernels of the tetrahedral path (gfx950): per-stage reconstruction
+// with TENO selection, HLL face fluxes, residual gather and SSP-RK3 update,
+// CFL time step.  Conservative variables (rho, rho u, rho v, rho w, E).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "internal3.h"
+
+namespace teno {
+namespace t3 {
+
+template <int P>
+struct O3 {
+  static constexpr int R = P - 1;
+  static constexpr int NU = (R + 1) * (R + 2) * (R + 3) / 6 - 1;  // large-stencil unknowns
+  static constexpr int NL = 2 * NU + 1;                           // its rows
+  static constexpr int NPT = P <= 4 ? 6 : 7;                      // points per face
+  static constexpr int RSL = NU + (NU & 1);                       // stored large row
+  static constexpr int ROWS = 4 * kSmall3Rows + NL;
+  static constexpr int JP = 4 * kSmall3Blk + NL * RSL;
+};
+
+struct Diag3 {
+  unsigned long long nonphysical;
+  unsigned long long near_ties;
+  unsigned long long fallbacks;
+  long long first_bad;  // LLONG_MAX when none
+};
+
+struct Recon3Args {
+  const double* __restrict__ U;        // [n][5]
+  const int32_t* __restrict__ idx;     // [n_tiles][rows][12] stencil members
+  const double2* __restrict__ M;       // [n_tiles][jp/2][12] operator entry pairs
+  // universal tables, staged in LDS by every block: psi [4 npt][nu] (basis at
+  // the face points), then the large and the small smoothness forms packed by
+  // rows of their upper triangles (diagonal, then doubled off-diagonals)
+  const double* __restrict__ tab;
+  double* __restrict__ fp;             // [4 npt][n_pad][5] face-point states
+  uint32_t* flags;                     // [n] 5 bits per variable (nullable)
+  const int32_t* __restrict__ user_of; // [n_pad]
+  Diag3* diag;
+  int n_cell, n_tiles, n_pad;
+  int variant, fallback, power;
+  double ct, eps, gamma, tie_lo, tie_hi;
+};
+
+template <int N>
+constexpr int packed3() {
+  return N * (N + 1) / 2;
+}
+
+__device__ __forceinline__ int xcd_remap3(int b, int nblk) {
+  const int X = 8;
+  const int q = nblk / X, r = nblk % X;
+  const int x = b % X, local = b / X;
+  return x * q + (x < r ? x : r) + local;
+}
+
+__device__ __forceinline__ double gamma3(double beta, double eps, int power) {
+  const double x = beta + eps;
+  double v = 1.0;
+  for (int t = 0; t < power; ++t) v *= x;
+  return 1.0 / v;
+}
+
+__device__ __forceinline__ int tie3(const Recon3Args& a, double chi) {
+  return (chi >= a.tie_lo && chi <= a.tie_hi) ? 1 : 0;
+}
+
+// Makes the table offset o depend on the running sum t: the table reads of
+// the next chunk cannot be issued before the arithmetic of this one, so the
+// compiler does not hoist every read of a fully unrolled loop (one register
+// pair per table entry) ahead of its use.
+__device__ __forceinline__ void chain3(int& o, double& t) {
+  asm volatile("" : "+v"(o), "+v"(t));
+}
+
+// a^T B a with B packed by rows of its upper triangle (diagonal first, the
+// off-diagonal entries doubled); T is an LDS table, read in chunks of eight
+template <int N>
+__device__ __forceinline__ double qform3(const double* T, const double (&x)[N]) {
+  double s = 0.0;
+  int o = 0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    double t = T[o] * x[l];
+#pragma unroll
+    for (int m = l + 1; m < N; ++m) {
+      t = fma(T[o + m - l], x[m], t);
+      if ((m - l) % 8 == 0) chain3(o, t);
+    }
+    s = fma(x[l], t, s);
+    o += N - l;
+    chain3(o, s);
+  }
+  return s;
+}
+
+// Least squares of one stencil for lane variable v (Sec. 2.2 eqs. 08-10):
+// acc = M d, d_s = U_member(s) - U_0, rows streamed in order; the member
+// state of the next row is loaded while the current row is accumulated.
+template <int ROWS, int JP, int NC, int RS>
+__device__ __forceinline__ void gemv3(const Recon3Args& a, int tile, int c, int v, int nr,
+                                      int row0, int j0, double u0, double (&acc)[NC]) {
+  const int32_t* __restrict__ ip = a.idx + ((size_t)tile * ROWS + row0) * kTile3 + c;
+  const double2* __restrict__ mp = a.M + ((size_t)tile * (JP / 2) + j0 / 2) * kTile3 + c;
+#pragma unroll
+  for (int l = 0; l < NC; ++l) acc[l] = 0.0;
+  double x = a.U[(size_t)ip[0] * kVars3 + v];
+#pragma unroll 1
+  for (int s = 0; s < nr; ++s) {
+    const int sn = s + 1 < nr ? s + 1 : s;
+    const double xn = a.U[(size_t)ip[(size_t)sn * kTile3] * kVars3 + v];
+    const double d = x - u0;
+    const double2* __restrict__ mr = mp + (size_t)(s * (RS / 2)) * kTile3;
+#pragma unroll
+    for (int q = 0; q < RS / 2; ++q) {
+      typedef double v2d __attribute__((ext_vector_type(2)));
+      const v2d m = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(&mr[(size_t)q * kTile3]));
+      acc[2 * q] = fma(m.x, d, acc[2 * q]);
+      if (2 * q + 1 < NC) acc[2 * q + 1] = fma(m.y, d, acc[2 * q + 1]);
+    }
+    x = xn;
+  }
+}
+
+__device__ __forceinline__ bool physical3(double r, double mx, double my, double mz, double e,
+                                          double g) {
+  if (!(r > 0.0)) return false;
+  const double p = (g - 1.0) * (e - 0.5 * (mx * mx + my * my + mz * mz) / r);
+  return p > 0.0;  // false for NaN
+}
+
+// Reconstruction of one tile (12 cells, lane = 5 c + v) in four passes that
+// keep few coefficient vectors live: the indicators of the four small
+// stencils (their coefficients are dropped), the large stencil's
+// coefficients and indicator, the selection of Sec. 3.3 with K = 4, and -
+// only where the large stencil is rejected - the coefficients of the kept
+// small stencils again, averaged.  Face values of the selected polynomial are
+// written as they are formed.
+template <int P>
+__global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
+  using O = O3<P>;
+  constexpr int NU = O::NU, NPT = O::NPT, NP = 4 * NPT;
+  constexpr int NPSI = NP * NU, NBL = packed3<NU>(), NBS = packed3<kSmall3Coef>();
+  __shared__ double tab[NPSI + NBL + NBS];
+  for (int i = threadIdx.x; i < NPSI + NBL + NBS; i += 256) tab[i] = a.tab[i];
+  __syncthreads();
+  const double* psi = tab;
+  const double* Bl = tab + NPSI;
+  const double* Bs = tab + NPSI + NBL;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tile = __builtin_amdgcn_readfirstlane(xcd_remap3(blockIdx.x, gridDim.x) * 4 + wave);
+  if (tile >= a.n_tiles) return;  // whole wavefront leaves together; no barrier follows
+  const int c = lane < 60 ? lane / kVars3 : kTile3 - 1;
+  const int v = lane < 60 ? lane - kVars3 * c : 0;
+  const int cell = tile * kTile3 + c;
+  const bool live = lane < 60 && cell < a.n_cell;
+  const int cl = cell < a.n_cell ? cell : tile * kTile3;
+  const double u0 = a.U[(size_t)cl * kVars3 + v];
+
+  // ---- large stencil ----
+  double co[NU];
+  gemv3<O::ROWS, O::JP, NU, O::RSL>(a, tile, c, v, O::NL, 4 * kSmall3Rows, 4 * kSmall3Blk, u0, co);
+  // ---- selection (Sec. 3.2-3.3, K = 4); the linear scheme keeps the large
+  // stencil and never reads the small ones.  Each indicator is formed in the
+  // block that uses it, so that its table reads are not hoisted apart from
+  // its arithmetic.
+  unsigned nib = 0x10u;
+  int ties = 0;
+  if (a.variant == 0) {
+    double g[4], gs = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      double as[kSmall3Coef];
+      gemv3<O::ROWS, O::JP, kSmall3Coef, kSmall3Stored>(a, tile, c, v, kSmall3Rows,
+                                                        k * kSmall3Rows, k * kSmall3Blk, u0, as);
+      const double gk = gamma3(qform3<kSmall3Coef>(Bs, as), a.eps, a.power);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q == k) g[q] = gk;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gs += g[k];
+    const double gK = gamma3(qform3<NU>(Bl, co), a.eps, a.power);
+    const double chiK = gK / (gs + gK);
+    ties += tie3(a, chiK);
+    if (chiK < a.ct) {
+      nib = 0u;
+      const double is = 1.0 / gs;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double x = g[k] * is;
+        ties += tie3(a, x);
+        if (x >= a.ct) nib |= 1u << k;
+      }
+    }
+  }
+  // ---- large stencil rejected: the mean of the kept small stencils ----
+  if (!(nib & 0x10u)) {
+    double ab[kSmall3Coef];
+#pragma unroll
+    for (int l = 0; l < kSmall3Coef; ++l) ab[l] = 0.0;
+    int cnt = 0;
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      if (!((nib >> k) & 1u)) continue;
+      double as[kSmall3Coef];
+      gemv3<O::ROWS, O::JP, kSmall3Coef, kSmall3Stored>(a, tile, c, v, kSmall3Rows,
+                                                        k * kSmall3Rows, k * kSmall3Blk, u0, as);
+#pragma unroll
+      for (int l = 0; l < kSmall3Coef; ++l) ab[l] += as[l];
+      ++cnt;
+    }
+    // the small stencils' basis is the first nine functions of the large one
+#pragma unroll
+    for (int l = 0; l < NU; ++l) co[l] = (l < kSmall3Coef && cnt > 0) ? ab[l] / (double)cnt : 0.0;
+  }
+  // ---- face values, written as formed; the five lanes of a cell share
+  // their values for the physical-state test ----
+  const int b0 = kVars3 * c;
+  bool fp_ok = true;
+  double* out = a.fp + (size_t)cell * kVars3 + v;
+  const size_t qstride = (size_t)a.n_pad * kVars3;
+#pragma unroll 1
+  for (int q = 0; q < NP; ++q) {
+    double s = u0;
+    int o = q * NU;
+#pragma unroll
+    for (int l = 0; l < NU; ++l) {
+      s = fma(co[l], psi[o + l], s);
+      if (l % 8 == 7) chain3(o, s);
+    }
+    fp_ok = physical3(__shfl(s, b0), __shfl(s, b0 + 1), __shfl(s, b0 + 2), __shfl(s, b0 + 3),
+                      __shfl(s, b0 + 4), a.gamma) && fp_ok;
+    if (live) out[q * qstride] = s;
+  }
+  const bool avg_ok = physical3(__shfl(u0, b0), __shfl(u0, b0 + 1), __shfl(u0, b0 + 2),
+                                __shfl(u0, b0 + 3), __shfl(u0, b0 + 4), a.gamma);
+  if (live && v == 0 && !(avg_ok && fp_ok)) {
+    atomicAdd(&a.diag->nonphysical, 1ull);
+    atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
+  }
+  if (!fp_ok && avg_ok && a.fallback) {
+    if (live) {
+      for (int q = 0; q < NP; ++q) out[q * qstride] = u0;
+      if (v == 0) atomicAdd(&a.diag->fallbacks, 1ull);
+    }
+    nib = 0u;
+  }
+  if (live && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
+  if (a.flags) {
+    const unsigned f = nib << (5 * v);
+    const unsigned all = __shfl(f, b0) | __shfl(f, b0 + 1) | __shfl(f, b0 + 2) | __shfl(f, b0 + 3) |
+                         __shfl(f, b0 + 4);
+    if (live && v == 0) a.flags[cell] = all;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// HLL flux (Sec. 4) in the face normal: the rotated form of Sec. 4.1 written
+// without the rotation (the HLL flux with Einfeldt/Roe speeds commutes with
+// rotations), F = F(U_L) if S_L >= 0, F(U_R) if S_R <= 0, else the HLL mean.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void hll3(const double uL[5], const double uR[5], const double n[3],
+                                     double g, double F[5]) {
+  const double irL = 1.0 / uL[0], irR = 1.0 / uR[0];
+  const double vL[3] = {uL[1] * irL, uL[2] * irL, uL[3] * irL};
+  const double vR[3] = {uR[1] * irR, uR[2] * irR, uR[3] * irR};
+  const double pL = (g - 1.0) * (uL[4] - 0.5 * uL[0] * (vL[0] * vL[0] + vL[1] * vL[1] + vL[2] * vL[2]));
+  const double pR = (g - 1.0) * (uR[4] - 0.5 * uR[0] * (vR[0] * vR[0] + vR[1] * vR[1] + vR[2] * vR[2]));
+  const double unL = vL[0] * n[0] + vL[1] * n[1] + vL[2] * n[2];
+  const double unR = vR[0] * n[0] + vR[1] * n[1] + vR[2] * n[2];
+  const double cL = sqrt(g * pL * irL), cR = sqrt(g * pR * irR);
+  const double HL = (uL[4] + pL) * irL, HR = (uR[4] + pR) * irR;
+  const double D = sqrt(uR[0] * irL), iD = 1.0 / (1.0 + D);
+  double vt[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vt[a] = (vL[a] + D * vR[a]) * iD;
+  const double Ht = (HL + D * HR) * iD;
+  const double ct = sqrt((g - 1.0) * (Ht - 0.5 * (vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2])));
+  const double unt = vt[0] * n[0] + vt[1] * n[1] + vt[2] * n[2];
+  const double SL = fmin(unL - cL, unt - ct), SR = fmax(unR + cR, unt + ct);
+  const double FL[5] = {uL[0] * unL, uL[1] * unL + pL * n[0], uL[2] * unL + pL * n[1],
+                        uL[3] * unL + pL * n[2], (uL[4] + pL) * unL};
+  const double FR[5] = {uR[0] * unR, uR[1] * unR + pR * n[0], uR[2] * unR + pR * n[1],
+                        uR[3] * unR + pR * n[2], (uR[4] + pR) * unR};
+  if (SL >= 0.0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = FL[c];
+  } else if (SR <= 0.0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = FR[c];
+  } else {
+    const double is = 1.0 / (SR - SL);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = (SR * FL[c] - SL * FR[c] + SL * SR * (uR[c] - uL[c])) * is;
+  }
+}
+
+struct Flux3Args {
+  const double* __restrict__ fp;      // [4 npt][n_pad][5]
+  const int4* __restrict__ fcell;     // [n_face]: L, R (-1-b: boundary b), eL | eR << 2, pairing
+  const double4* __restrict__ fgeo;   // [n_face]: nx, ny, nz, |A|
+  const int* __restrict__ bkind;      // [n_bface]
+  double* __restrict__ phi;           // [n_face][5]
+  double w[7];                        // face rule weights
+  double gamma;
+  int n_face, n_pad;
+};
+
+template <int NPT>
+__global__ __launch_bounds__(256) void k_face_flux3(Flux3Args a) {
+  const int f = xcd_remap3(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (f >= a.n_face) return;
+  const int4 fc = a.fcell[f];
+  const double4 gg = a.fgeo[f];
+  const double n[3] = {gg.x, gg.y, gg.z};
+  const int eL = fc.z & 3, eR = fc.z >> 2;
+  double phi[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    double uL[5], uR[5];
+    const double* pl = a.fp + ((size_t)(eL * NPT + k) * a.n_pad + fc.x) * kVars3;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) uL[c] = pl[c];
+    if (fc.y >= 0) {
+      const int kr = (fc.w >> (3 * k)) & 7;
+      const double* pr = a.fp + ((size_t)(eR * NPT + kr) * a.n_pad + fc.y) * kVars3;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) uR[c] = pr[c];
+    } else {
+      // outer state of the boundary face: transmissive copies the inner
+      // state, reflective reverses its normal momentum
+#pragma unroll
+      for (int c = 0; c < 5; ++c) uR[c] = uL[c];
+      if (a.bkind[-1 - fc.y] == TENO_BC_REFLECTIVE) {
+        const double mn = uL[1] * n[0] + uL[2] * n[1] + uL[3] * n[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) uR[1 + d] = uL[1 + d] - 2.0 * mn * n[d];
+      }
+    }
+    double F[5];
+    hll3(uL, uR, n, a.gamma, F);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) phi[c] = fma(a.w[k], F[c], phi[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) a.phi[(size_t)f * 5 + c] = gg.w * phi[c];
+}
+
+struct Update3Args {
+  const int4* __restrict__ cfaces;    // [n_pad]: faces of local faces 0..3
+  const int* __restrict__ cside;      // [n_pad]: bit e when the cell is face e's L
+  const double* __restrict__ vol;     // [n_pad]: |V|
+  const double* __restrict__ phi;     // [n_face][5]
+  const double* Un;
+  const double* Uk;
+  double* out;                        // R or U^(k+1)
+  const double* dt;
+  double ca, cb, cc;
+  int n_cell, rk;
+};
+
+__global__ __launch_bounds__(256) void k_cell_update3(Update3Args a) {
+  const int t = xcd_remap3(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (t >= a.n_cell) return;
+  const int4 cf = a.cfaces[t];
+  const int side = a.cside[t];
+  const int fs[4] = {cf.x, cf.y, cf.z, cf.w};
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double* p = a.phi + (size_t)fs[e] * 5;
+    const bool isL = (side >> e) & 1;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] = isL ? acc[c] + p[c] : acc[c] - p[c];
+  }
+  const double ia = -1.0 / a.vol[t];
+  double* o = a.out + (size_t)t * 5;
+  if (a.rk) {
+    const double dt = *a.dt;
+    const double* un = a.Un + (size_t)t * 5;
+    const double* uk = a.Uk + (size_t)t * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = a.ca * un[c] + a.cb * uk[c] + a.cc * (dt * (acc[c] * ia));
+  } else {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = acc[c] * ia;
+  }
+}
+
+__device__ __forceinline__ double block_min3(double x, double* sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) x = fmin(x, sh[k]);
+    sh[0] = x;
+  }
+  __syncthreads();
+  return sh[0];
+}
+
+// |V_i| / sum_f |A_if| (|u_i . n_if| + c_i) per block, then cfl * min
+__global__ __launch_bounds__(256) void k_dt3_partial(const double* __restrict__ U,
+                                                     const double* __restrict__ geo, int n,
+                                                     double g, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  double lim = INFINITY;
+  if (t < n) {
+    const double* u = U + (size_t)t * 5;
+    const double* gg = geo + (size_t)t * 17;
+    const double ir = 1.0 / u[0];
+    const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+    const double p = (g - 1.0) * (u[4] - 0.5 * u[0] * (vx * vx + vy * vy + vz * vz));
+    const double c = sqrt(g * p * ir);
+    double den = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      den += gg[4 * e + 3] * (fabs(vx * gg[4 * e] + vy * gg[4 * e + 1] + vz * gg[4 * e + 2]) + c);
+    lim = gg[16] / den;
+  }
+  const double m = block_min3(lim, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_dt3_final(const double* __restrict__ partial, int n,
+                                                   double cfl, double* __restrict__ dt) {
+  __shared__ double sh[4];
+  double x = INFINITY;
+  for (int i = threadIdx.x; i < n; i += 256) x = fmin(x, partial[i]);
+  const double m = block_min3(x, sh);
+  if (threadIdx.x == 0) *dt = cfl * m;
+}
+
+__global__ void k_diag3_reset(Diag3* d) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    d->nonphysical = 0;
+    d->near_ties = 0;
+    d->fallbacks = 0;
+    d->first_bad = LLONG_MAX;
+  }
+}
+
+}  // namespace t3
+}  // namespace teno

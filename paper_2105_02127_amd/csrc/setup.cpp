@@ -396,7 +396,7 @@ struct Radon {
 // Householder QR of the m x n row-major matrix A, then
 //   Op[l][s] = (R^{-1} Q_1^T)[l][s] * scale[s].
 // Returns min|R_jj|/max|R_jj| (0 on breakdown).
-static double pinv_scaled(int m, int n, std::vector<double>& A, const double* scale, double* Op) {
+double pinv_scaled(int m, int n, std::vector<double>& A, const double* scale, double* Op) {
   // A row-major [m][n]; Householder vectors stored in place below the diagonal
   std::vector<double> vj(m), beta(n);
   for (int j = 0; j < n; ++j) {

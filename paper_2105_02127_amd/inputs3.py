@@ -198,11 +198,14 @@ def explosion3(mesh: TetMesh, centre=(0.0, 0.0, 0.0), radius: float = 0.5) -> np
 
 # Workloads on tetrahedra: TENO on the jittered periodic cube (random planes
 # or the smooth wave), and the paper's 3D explosion (Sec. 5.9: edge h ~ 1/30)
-# on [-1, 1]^3 with transmissive sides, 60^3 x 6 = 1,296,000 cells.
+# on [-1, 1]^3 with transmissive sides, 60^3 x 6 = 1,296,000 cells.  fallback:
+# cells whose reconstruction leaves the physical states at a face point use
+# their average there (the strong jumps need it).
 WORKLOADS3 = {
-    "teno4_planes_N32": dict(order=4, n=32, seed=31, ic="random_planes"),
-    "teno3_wave_N12": dict(order=3, n=12, seed=32, ic="smooth_wave"),
-    "explosion3_N60": dict(order=4, n=60, seed=33, ic="explosion", box=((-1.0,) * 3, (1.0,) * 3)),
+    "teno4_planes_N32": dict(order=4, n=32, seed=31, ic="random_planes", fallback=1),
+    "teno3_wave_N12": dict(order=3, n=12, seed=32, ic="smooth_wave", fallback=0),
+    "explosion3_N60": dict(order=4, n=60, seed=33, ic="explosion", box=((-1.0,) * 3, (1.0,) * 3),
+                           fallback=1),
 }
 
 

@@ -129,3 +129,39 @@ def trajectory(torch, sv, om, U_user, perm, steps, cfl=0.4, label="", log=print,
         Un = bufs[2].clone()
         U = ref["U"]
     return resyncs, worst, U
+
+
+def _fields5(x):
+    """Count of nonzero 5-bit fields of a uint32 array (five variables)."""
+    x = np.asarray(x, dtype=np.uint32)
+    return int(sum(((x >> (5 * v)) & 0x1F != 0).sum() for v in range(5)))
+
+
+def check_flags5(gpu, orc, tie_mask, what="flags"):
+    """Tetrahedral flags (5 bits per variable) equal outside the oracle's
+    near ties; returns the number of fields that differ inside them."""
+    g = np.asarray(gpu, dtype=np.uint32)
+    o = np.asarray(orc, dtype=np.uint32)
+    t = np.asarray(tie_mask, dtype=np.uint32)
+    assert g.shape == o.shape == t.shape, (g.shape, o.shape, t.shape)
+    d = g ^ o
+    away = d & ~t
+    if away.any():
+        idx = np.argwhere(away != 0)[:8].tolist()
+        raise AssertionError(f"{what}: {_fields5(away)} flag fields differ away from near ties "
+                             f"(first at {idx}: gpu {g[tuple(idx[0])]:#09x} oracle "
+                             f"{o[tuple(idx[0])]:#09x})")
+    return _fields5(d)
+
+
+def assert_states5(x, y, rel=REL, what="state"):
+    """Per conservative variable of the five: max |x - y| <= rel max |y|."""
+    x = np.asarray(x).reshape(-1, 5)
+    y = np.asarray(y).reshape(-1, 5)
+    worst = 0.0
+    for v in range(5):
+        err = np.abs(x[:, v] - y[:, v]).max()
+        ref = np.abs(y[:, v]).max()
+        assert err <= rel * ref, f"{what} variable {v}: max err {err:.3e} vs {rel:.0e} * {ref:.3e}"
+        worst = max(worst, err / ref if ref > 0 else err)
+    return worst
