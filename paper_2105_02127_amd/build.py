@@ -34,7 +34,7 @@ def build(verbose: bool = False, resource_usage: bool = False, lib: str = LIB,
     os.makedirs(BUILD, exist_ok=True)
     extra_hip = list(extra_hip_flags or []) + os.environ.get("TENO_HIPCC_EXTRA", "").split()
     # layout macros must reach both the host set-up and the kernels
-    layout = [f for f in extra_hip if f.startswith("-DTENO_TILE")]
+    layout = [f for f in extra_hip if f.startswith(("-DTENO_TILE", "-DTENO_DENSE", "-DTENO_LARGE"))]
     setup_o = os.path.join(BUILD, "setup.o")
     setup3_o = os.path.join(BUILD, "setup3.o")
     api_o = os.path.join(BUILD, "teno_api.o")

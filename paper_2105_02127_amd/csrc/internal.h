@@ -30,10 +30,11 @@ struct Dims {
   int rows4 = 0;   // rows rounded up to a multiple of 4 (int4 loads)
   int J = 0;       // operator entries per cell: 3 * 5 * 11 + nu * nl
   int lblk = 0;    // stored entries of the large stencil (see block_entries)
-  int Jp = 0;      // stored entries per cell: 3 * kSmallBlock + lblk
+  int Jp = 0;      // stored entries per cell: 3 small blocks + lblk
+  bool dense = true;  // operator blocks of odd row length stored rows by lane
 };
 
-Dims dims_for(int order, int nq_req);
+Dims dims_for(int order, int nq_req, bool dense);
 
 // Largest number of distinct stencil members a 16-cell tile may have (their
 // states are staged in LDS, 32 bytes each).
@@ -106,24 +107,59 @@ struct Mesh {
 constexpr int small_row(int k, int s) { return kSmallRows * k + s; }
 constexpr int large_row(int s) { return 3 * kSmallRows + s; }
 
-// Stored operator entries of one stencil (M^T, nrow rows of L coefficients):
-// rows back to back, each padded with a zero to an even length so that a
-// 16-byte pair never straddles two rows.  (Packing the entries densely
-// needs more lanes or registers per row in the kernel and measured slower
-// than streaming the padding.)
+// Stored operator entries of one stencil (M^T: nrow rows of L
+// coefficients), in one of two block layouts (offsets in doubles within the
+// block of a tile of kTile cells):
+//  * rows by lane (dense meshes, odd L: the small stencils and the large one
+//    at orders 3 and 4): the rows come in groups of four; lane g of a cell
+//    owns row 4j + g of group j and reads its L entries from L planes, each
+//    holding entry l of the group's rows for every cell (cell-major,
+//    row-minor).  The last group may hold fewer rows.  Nothing is padded,
+//    and a wavefront's load of one plane covers 16 cells x 4 rows
+//    contiguously.
+//  * entry pairs (even L, or any L on meshes that are not dense): M^T row by
+//    row as 16-byte pairs, [pair][cell][2], odd rows padded with a zero to
+//    even length; lane g of a cell reads pairs g, g + 4, ... of each row.
+// Meshes reconstructed in conservative variables are dense; the
+// characteristic-variable kernel holds more values across its streams and
+// measured faster on entry pairs.  TENO_DENSE=0 makes no mesh dense.
+#ifndef TENO_DENSE
+#define TENO_DENSE 1
+#endif
+#ifndef TENO_LARGE_LANES
+#define TENO_LARGE_LANES 1
+#endif
+constexpr bool lane_rows(int L, bool dense) { return TENO_DENSE && dense && (L & 1) && kTile == 16; }
+// the large stencil's block (its rows are longer than the small ones')
+constexpr bool large_lane_rows(int L, bool dense) { return TENO_LARGE_LANES && lane_rows(L, dense); }
 constexpr int stored_row(int L) { return L + (L & 1); }
-constexpr int block_entries(int nrow, int L) { return nrow * stored_row(L); }
-constexpr int entry_in_block(int L, int s, int l) { return s * stored_row(L) + l; }
-constexpr int kSmallBlock = block_entries(kSmallRows, kSmallCoef);  // 66
+constexpr int block_entries(int nrow, int L, bool dense) {
+  return lane_rows(L, dense) ? nrow * L : nrow * stored_row(L);
+}
+constexpr int group_rows(int nrow, int j) { return nrow - 4 * j < 4 ? nrow - 4 * j : 4; }
+constexpr int block_offset(int nrow, int L, bool dense, int c, int s, int l) {
+  return lane_rows(L, dense)
+             ? 4 * kTile * L * (s / 4) + (l * kTile + c) * group_rows(nrow, s / 4) + (s % 4)
+             : (((s * stored_row(L) + l) >> 1) * kTile + c) * 2 + ((s * stored_row(L) + l) & 1);
+}
+constexpr int small_block(bool dense) { return block_entries(kSmallRows, kSmallCoef, dense); }
+constexpr int large_block(int nrow, int L, bool dense) {
+  return block_entries(nrow, L, large_lane_rows(L, dense));
+}
+constexpr int large_block_offset(int nrow, int L, bool dense, int c, int s, int l) {
+  return block_offset(nrow, L, large_lane_rows(L, dense), c, s, l);
+}
 
-// Stored entry of the operator stream of one cell: the three small stencils'
-// blocks, then the large stencil's.  Layout [tile][j/2][cell][2]: a lane
-// reads both entries of a pair with one 16-byte load.
-inline int entry_small(int k, int s, int l) { return kSmallBlock * k + entry_in_block(kSmallCoef, s, l); }
-inline int entry_large(const Dims& d, int s, int l) { return 3 * kSmallBlock + entry_in_block(d.nu, s, l); }
-inline int64_t packed_M_index(const Mesh& m, int internal, int j) {
-  int t = internal / kTile, c = internal % kTile;
-  return (((int64_t)t * (m.d.Jp / 2) + (j >> 1)) * kTile + c) * 2 + (j & 1);
+// The operator stream of a tile: the three small stencils' blocks, then the
+// large stencil's, Jp * kTile doubles in all.  Block k (3 = large) starts at
+// block_start(k, dense) * kTile.
+constexpr int block_start(int k, bool dense) { return small_block(dense) * k; }
+inline int64_t packed_M_offset(const Dims& d, int internal, int k, int s, int l) {
+  const int t = internal / kTile, c = internal % kTile;
+  const bool big = k == 3;
+  return ((int64_t)t * d.Jp + block_start(k, d.dense)) * kTile +
+         (big ? large_block_offset(d.nl, d.nu, d.dense, c, s, l)
+              : block_offset(kSmallRows, kSmallCoef, d.dense, c, s, l));
 }
 
 inline int64_t packed_idx_index(const Mesh& m, int internal, int row) {

@@ -259,7 +259,7 @@ struct ReconArgs {
   const int* __restrict__ tmem;        // [n_tiles][ustride] distinct members of a tile
   int ustride;                         // members per tile list
   int lds_stride;                      // LDS per wavefront in int4 (stage_int4)
-  const double2* __restrict__ M;       // [n_tiles][JP/2][kTile] entry pairs
+  const double2* __restrict__ M;       // [n_tiles][JP * kTile] doubles: the tile's blocks
   double* __restrict__ fp;             // [3 nq][n_pad][4]
   uint16_t* flags;                     // out, or in when frozen
   const int32_t* __restrict__ user_of; // [n_pad]
@@ -369,18 +369,18 @@ __device__ __forceinline__ void static_for(F&& f) {
 #define TENO_M_NONTEMPORAL 1
 #endif
 
-template <int R0, int NR, int J0, int RS>
+template <int R0, int NR, int RS>
 struct RowStream {
   static constexpr int NB = TENO_ROW_BUFFERS;
   static constexpr int LPC = kLanesPerCell;
   static constexpr int NPAIR = RS / 2;                // pairs per row
   static constexpr int NT = (NPAIR + LPC - 1) / LPC;  // pair slots per lane
-  static_assert(RS % 2 == 0 && J0 % 2 == 0, "rows are whole pairs");
+  static_assert(RS % 2 == 0, "rows are whole pairs");
   using Acc = double[NT][2][4];
 
   const double* us;                    // LDS: states of the tile's distinct members
   const uint16_t* sidx;                // LDS: each stencil row's member slot
-  const double2* __restrict__ mp;
+  const double2* __restrict__ mp;      // this cell's pairs of the block
   int c, g;
   double u0g;
   double xq[NB];
@@ -391,7 +391,7 @@ struct RowStream {
     const int r = R0 + s;
     const int id = sidx[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
     x = us[id * 4 + (g & 3)];
-    const double2* __restrict__ mr = mp + (size_t)((J0 + s * RS) / 2) * kTile;
+    const double2* __restrict__ mr = mp + (size_t)(s * RS / 2) * kTile;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       // Lanes past the row's last pair re-read that pair: the load stays
@@ -456,6 +456,109 @@ struct RowStream {
       return pick4(__shfl(acc[t][k][0], sl), __shfl(acc[t][k][1], sl), __shfl(acc[t][k][2], sl),
                    __shfl(acc[t][k][3], sl), v);
     }
+  }
+};
+
+// The same least-squares phase for a block stored rows by lane (odd L, see
+// block_offset): the NR rows come in groups of four, lane g of a cell owns
+// row 4j + g of group j and adds all L entries of it into all four
+// variables, acc[l][v] += M_l d_v, with d read from the staged member states
+// (all four variables of the member).  Every lane's loads are distinct and
+// contiguous across the wavefront, and no difference is broadcast.  Lanes
+// past the last group's rows re-read its last row with d = 0.  The groups
+// are few (3 for a small stencil, 5 for the large one at order 4) and fully
+// unrolled; NB of them are in flight.  coef<l>() sums the four lanes'
+// partial sums of coefficient l in a fixed order (lanes {0,1} and {2,3}
+// first) and hands lane g variable g.
+#ifndef TENO_LANE_BUFFERS
+#define TENO_LANE_BUFFERS 2
+#endif
+
+template <class T>
+struct TypeTag {
+  using type = T;
+};
+
+template <int K>
+__device__ __forceinline__ double quad_perm_dpp(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), K, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), K, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int R0, int NR, int L>
+struct RowLanes {
+  static constexpr int NG = (NR + 3) / 4;
+  static constexpr int NB = TENO_LANE_BUFFERS < NG ? TENO_LANE_BUFFERS : NG;
+  static_assert(kTile == 16, "rows by lane need four lanes per cell");
+  using Acc = double[L][4];
+
+  const double* us;                    // LDS: states of the tile's distinct members
+  const uint16_t* sidx;                // LDS: each stencil row's member slot
+  const double* __restrict__ mb;       // the tile's block
+  int c, g;
+  double u0[4];                        // the cell's means, all four variables
+  double xq[NB][4];
+  double mq[NB][L];
+
+  template <int J>
+  __device__ __forceinline__ void issue(double (&x)[4], double (&m)[L]) const {
+    constexpr int rg = group_rows(NR, J);
+    const int gg = g < rg ? g : rg - 1;
+    const int r = R0 + 4 * J + gg;
+    const int id = sidx[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
+    const double2* u = reinterpret_cast<const double2*>(us + id * 4);
+    const double2 a0 = u[0], a1 = u[1];
+    x[0] = a0.x;
+    x[1] = a0.y;
+    x[2] = a1.x;
+    x[3] = a1.y;
+    const double* __restrict__ p = mb + 4 * kTile * L * J + c * rg + gg;
+#pragma unroll
+    for (int l = 0; l < L; ++l) m[l] = __builtin_nontemporal_load(p + l * kTile * rg);
+  }
+
+  template <int J>
+  __device__ __forceinline__ void accumulate(const double (&x)[4], const double (&m)[L],
+                                             Acc& acc) const {
+    constexpr int rg = group_rows(NR, J);
+    const bool on = rg == 4 || g < rg;
+    double d[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = on ? x[v] - u0[v] : 0.0;
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[l][v] = fma(m[l], d[v], acc[l][v]);
+  }
+
+  __device__ __forceinline__ void prime() {
+    static_for<0, NB - 1>([&](auto k) { issue<k>(xq[k], mq[k]); });
+  }
+
+  __device__ __forceinline__ void run(Acc& acc) {
+    static_for<0, NG>([&](auto j) {
+      constexpr int nj = j + NB - 1;
+      if constexpr (nj < NG) issue<nj>(xq[nj % NB], mq[nj % NB]);
+      accumulate<j>(xq[j % NB], mq[j % NB], acc);
+    });
+  }
+
+  // Coefficient l of variable v = g: reduce-scatter over the cell's four
+  // lanes.  Lane g keeps the variables of its parity and takes its
+  // neighbour's (g ^ 1) sums of them, then keeps variable g and takes
+  // lane g ^ 2's pair sum of it.  Called with all four lanes active.
+  template <int l>
+  __device__ __forceinline__ static double coef(const Acc& acc, int v, int lane) {
+    const bool odd = lane & 1, hi = lane & 2;
+    const double k0 = odd ? acc[l][1] : acc[l][0];
+    const double k1 = odd ? acc[l][3] : acc[l][2];
+    const double s0 = odd ? acc[l][0] : acc[l][1];
+    const double s1 = odd ? acc[l][2] : acc[l][3];
+    const double p0 = k0 + quad_perm_dpp<0xB1>(s0);  // quad_perm(1, 0, 3, 2)
+    const double p1 = k1 + quad_perm_dpp<0xB1>(s1);
+    const double keep = hi ? p1 : p0, send = hi ? p0 : p1;
+    return keep + quad_perm_dpp<0x4E>(send);  // quad_perm(2, 3, 0, 1)
   }
 };
 
@@ -825,7 +928,15 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   const int cell = tile * kTile + c;
   const bool live = cell < a.n_cell;
   const double u0 = a.U[(size_t)(live ? cell : 0) * 4 + v];
-  const double2* __restrict__ mp = a.M + (size_t)tile * (O::JP / 2) * kTile + c;
+  // the tile's operator stream (JP doubles per cell) and its blocks; meshes
+  // in conservative variables are dense
+  constexpr bool D = !CH;
+  constexpr int JP = O::template JPD<D>;
+  const double* __restrict__ mt = reinterpret_cast<const double*>(a.M) + (size_t)tile * JP * kTile;
+  auto pairs = [&](int k) {
+    return reinterpret_cast<const double2*>(mt + (size_t)block_start(k, D) * kTile) + c;
+  };
+  auto lanes = [&](int k) { return mt + (size_t)block_start(k, D) * kTile; };
   const bool frozen = a.frozen != 0;
   const unsigned nib_in = (frozen && live) ? ((a.flags[cell] >> (4 * v)) & 0xFu) : 8u;
 
@@ -833,16 +944,38 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   //      needs only their indicators.  Each stream is started before the
   //      previous stencil's coefficients are gathered, and the large
   //      stencil's first rows load during that last step ----
-  using LargeS = RowStream<33, O::NL, 3 * O::SBLK, stored_row(O::NU)>;
-  LargeS ls{us, sidx, mp, c, g, u0};
+  constexpr bool LL = large_lane_rows(O::NU, D), SL = lane_rows(kSmallCoef, D);
+  using LargeS = std::conditional_t<LL, RowLanes<33, O::NL, O::NU>,
+                                    RowStream<33, O::NL, stored_row(O::NU)>>;
+  double u0q[4] = {u0, u0, u0, u0};
+  if constexpr (LL || SL) {
+    u0q[0] = quad_bcast<0>(u0);
+    u0q[1] = quad_bcast<1>(u0);
+    u0q[2] = quad_bcast<2>(u0);
+    u0q[3] = quad_bcast<3>(u0);
+  }
+  auto make_large = [&]() {
+    if constexpr (LL)
+      return LargeS{us, sidx, lanes(3), c, g, {u0q[0], u0q[1], u0q[2], u0q[3]}};
+    else
+      return LargeS{us, sidx, pairs(3), c, g, u0};
+  };
+  LargeS ls = make_large();
   double as[3][5];
   {
-    using S0 = RowStream<0, 11, 0, stored_row(5)>;
-    using S1 = RowStream<11, 11, O::SBLK, stored_row(5)>;
-    using S2 = RowStream<22, 11, 2 * O::SBLK, stored_row(5)>;
-    S0 s0{us, sidx, mp, c, g, u0};
-    S1 s1{us, sidx, mp, c, g, u0};
-    S2 s2{us, sidx, mp, c, g, u0};
+    using S0 = std::conditional_t<SL, RowLanes<0, 11, 5>, RowStream<0, 11, stored_row(5)>>;
+    using S1 = std::conditional_t<SL, RowLanes<11, 11, 5>, RowStream<11, 11, stored_row(5)>>;
+    using S2 = std::conditional_t<SL, RowLanes<22, 11, 5>, RowStream<22, 11, stored_row(5)>>;
+    auto make = [&](auto tag, int k) {
+      using S = typename decltype(tag)::type;
+      if constexpr (SL)
+        return S{us, sidx, lanes(k), c, g, {u0q[0], u0q[1], u0q[2], u0q[3]}};
+      else
+        return S{us, sidx, pairs(k), c, g, u0};
+    };
+    S0 s0 = make(TypeTag<S0>{}, 0);
+    S1 s1 = make(TypeTag<S1>{}, 1);
+    S2 s2 = make(TypeTag<S2>{}, 2);
     typename S0::Acc sk0 = {}, sk1 = {}, sk2 = {};
     s0.prime();
     s0.run(sk0);
@@ -920,8 +1053,20 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
   }
 }
 
+// Per-order occupancy targets (waves per SIMD; 1 leaves the budget to the
+// compiler): order 3 in rows-by-lane blocks needs 132 registers left alone
+// and runs faster held to 128 (four waves); the other orders measured best
+// unconstrained.
+template <int P, bool CW>
+struct ReconWaves {
+  static constexpr int value = TENO_RECON_WAVES_PER_EU > 0 ? TENO_RECON_WAVES_PER_EU
+                               : (P == 3 && !CW && lane_rows(kSmallCoef, true)) ? 4
+                                                                           : 1;
+};
+
 template <int P, int NQ, bool CW>
-__global__ __launch_bounds__(256) TENO_RECON_ATTR void k_reconstruct(ReconArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ReconWaves<P, CW>::value)))
+void k_reconstruct(ReconArgs a) {
   extern __shared__ int4 lds[];  // 4 wavefronts x a.lds_stride
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
@@ -1331,10 +1476,17 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
 #pragma unroll
     for (int l = 0; l < NU; ++l) ab[l] = fma(FaceBasis<O::R, NQ>::P.v[q][l], gq, ab[l]);
   }
-  // stored entry j of this cell: component j%2 of pair j/2
-  const double* __restrict__ mp =
-      reinterpret_cast<const double*>(a.M + (size_t)tile * (O::JP / 2) * kTile + c);
-  auto entry = [&](int j) { return mp[(size_t)(j >> 1) * (2 * kTile) + (j & 1)]; };
+  // entry (s, l) of this cell's stencil k (3 = large) in the tile's stream
+  // (the adjoint runs on meshes in conservative variables: dense)
+  const double* __restrict__ mt =
+      reinterpret_cast<const double*>(a.M) + (size_t)tile * O::template JPD<true> * kTile;
+  auto small_entry = [&](int k, int s, int l) {
+    return mt[(size_t)block_start(k, true) * kTile +
+              block_offset(kSmallRows, kSmallCoef, true, c, s, l)];
+  };
+  auto large_entry = [&](int s, int l) {
+    return mt[(size_t)block_start(3, true) * kTile + large_block_offset(O::NL, NU, true, c, s, l)];
+  };
   const uint16_t* __restrict__ sl =
       reinterpret_cast<const uint16_t*>(a.aslot + (size_t)tile * slot_int4(O::ROWS4));
   const int rounds = a.tround[tile];  // >= 1, the same for the whole wavefront
@@ -1363,7 +1515,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
       for (int s = 0; s < 11; ++s) {
         double d = 0.0;
 #pragma unroll
-        for (int l = 0; l < 5; ++l) d = fma(entry(k * O::SBLK + entry_in_block(5, s, l)), ab[l], d);
+        for (int l = 0; l < 5; ++l) d = fma(small_entry(k, s, l), ab[l], d);
         d *= wk;
         dsum += d;
         add_row(small_row(k, s), d);
@@ -1375,10 +1527,7 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
     for (int s = 0; s < O::NL; ++s) {
       double d = 0.0;
 #pragma unroll
-      for (int l = 0; l < NU; ++l) {
-        const int j = 3 * O::SBLK + entry_in_block(NU, s, l);
-        d = fma(entry(j), ab[l], d);
-      }
+      for (int l = 0; l < NU; ++l) d = fma(large_entry(s, l), ab[l], d);
       dsum += d;
       add_row(large_row(s), d);
     }

@@ -33,7 +33,7 @@ int fail(int code, const std::string& msg) {
 }
 const char* last_error() { return g_error.c_str(); }
 
-Dims dims_for(int order, int nq_req) {
+Dims dims_for(int order, int nq_req, bool dense) {
   Dims d;
   d.order = order;
   d.r = order - 1;
@@ -44,8 +44,9 @@ Dims dims_for(int order, int nq_req) {
   d.rows = 3 * kSmallRows + d.nl;
   d.rows4 = (d.rows + 3) / 4;
   d.J = 3 * kSmallCoef * kSmallRows + d.nu * d.nl;
-  d.lblk = block_entries(d.nl, d.nu);
-  d.Jp = 3 * kSmallBlock + d.lblk;
+  d.dense = dense;
+  d.lblk = large_block(d.nl, d.nu, dense);
+  d.Jp = 3 * small_block(dense) + d.lblk;
   return d;
 }
 
@@ -512,7 +513,7 @@ int mesh_setup(Mesh& m, const teno_params& p) {
   if (p.power < 1 || p.power > 16) return fail(TENO_EARG, "power must be 1..16");
   if (p.n_quad != 0 && (p.n_quad < 2 || p.n_quad > 3)) return fail(TENO_EARG, "n_quad must be 0, 2 or 3");
   m.prm = p;
-  m.d = dims_for(p.order, p.n_quad);
+  m.d = dims_for(p.order, p.n_quad, p.characteristic == 0);
   const Dims& d = m.d;
   const int nc = m.nc;
   // stencil rows are addressed as cell * 4 ceil(rows / 4) + row in 32 bits
@@ -601,8 +602,7 @@ int mesh_setup(Mesh& m, const teno_params& p) {
       for (int s = 0; s < nrow; ++s) {
         m.idx[packed_idx_index(m, t, big ? large_row(s) : small_row(k, s))] = m.inv[mem[s]];
         for (int l = 0; l < B.n; ++l)
-          m.M[packed_M_index(m, t, big ? entry_large(d, s, l) : entry_small(k, s, l))] =
-              op[(size_t)l * nrow + s];
+          m.M[packed_M_offset(d, t, k, s, l)] = op[(size_t)l * nrow + s];
       }
     }
     std::lock_guard<std::mutex> g(mu);

@@ -144,9 +144,9 @@ struct OrderT {
   static constexpr int ROWS = 33 + NL;
   static constexpr int ROWS4 = (ROWS + 3) / 4;
   static constexpr int J = 165 + NU * NL;         // operator entries
-  static constexpr int SBLK = block_entries(11, 5);    // stored entries per small stencil
-  static constexpr int LBLK = block_entries(NL, NU);    // stored large-stencil entries
-  static constexpr int JP = 3 * SBLK + LBLK;            // stored entries per cell
+  // stored entries per cell of a dense mesh (D) or of one on entry pairs
+  template <bool D>
+  static constexpr int JPD = 3 * small_block(D) + large_block(NL, NU, D);
 };
 
 }  // namespace teno

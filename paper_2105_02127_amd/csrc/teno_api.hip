@@ -508,8 +508,7 @@ int teno_mesh_lsq_operator(const teno_mesh* m, int32_t cell, int32_t k, double* 
   const int nrow = big ? x.d.nl : kSmallRows, nco = big ? x.d.nu : kSmallCoef;
   for (int l = 0; l < nco; ++l)
     for (int s = 0; s < nrow; ++s)
-      M[(size_t)l * nrow + s] =
-          x.M[packed_M_index(x, t, big ? entry_large(x.d, s, l) : entry_small(k, s, l))];
+      M[(size_t)l * nrow + s] = x.M[packed_M_offset(x.d, t, k, s, l)];
   return nrow;
 }
 
