@@ -1426,16 +1426,19 @@ __global__ __launch_bounds__(256) void k_adj_boundary(AdjFaceArgs a, const int* 
   }
 }
 
-// Phase 2 (one wavefront per tile, one lane per (cell, variable)):
-// transpose of the reconstruction.  The adjoint of each stencil difference
-// d_s = U_s - U_0 goes to the tile's member slot of U_s, summed in LDS (one
-// accumulator per distinct member and variable) in a fixed order: rows in
-// program order, and within a row the cells that name the same member in
-// rounds, in cell order (set-up assigns the rounds), so that no LDS
-// instruction has two lanes on one address and every sum is formed in the
-// same order on every run.  The tile's sums are written once to tbar; the
-// cell's own part (the -U_0 of its differences and its face points) goes to
-// own[n][4].
+// Phase 2 (one wavefront per tile, four lanes per cell): transpose of the
+// reconstruction.  The adjoint of each stencil difference d_s = U_s - U_0
+// goes to the tile's member slot of U_s, summed in LDS (one accumulator per
+// distinct member and variable) in a fixed order.  Blocks stored rows by
+// lane are read as the forward kernel reads them: lane g of a cell takes row
+// 4j + g of group j for all four variables (the coefficient adjoints of the
+// cell are shared across its four lanes first); blocks of entry pairs are
+// read by lane v for variable v, row by row.  Within one LDS instruction the
+// lanes that name the same member add in rounds that set-up assigns (in lane
+// order for a group of rows, in cell order for one row), so no instruction
+// has two lanes on one address and every sum is formed in the same order on
+// every run.  The tile's sums are written once to tbar; the cell's own part
+// (the -U_0 of its differences and its face points) goes to own[n][4].
 struct AdjReconArgs {
   const double* __restrict__ fpbar;
   const uint16_t* __restrict__ flags;
@@ -1448,11 +1451,22 @@ struct AdjReconArgs {
   int n_cell, n_tiles, n_pad;
 };
 
+__device__ __forceinline__ unsigned quad_bcast_u(unsigned x, int k) {
+  switch (k) {
+    case 0: return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x00, 0xF, 0xF, false);
+    case 1: return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x55, 0xF, 0xF, false);
+    case 2: return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0xAA, 0xF, 0xF, false);
+    default: return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0xFF, 0xF, 0xF, false);
+  }
+}
+
 template <int P, int NQ>
 __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
+  constexpr bool SL = lane_rows(kSmallCoef, true), LL = large_lane_rows(NU, true);
+  static_assert(kTile == 16, "four lanes per cell");
   extern __shared__ double lds_acc[];  // 4 wavefronts x ustride x 4
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tile = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
@@ -1460,9 +1474,9 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
   double* acc = lds_acc + (size_t)wave * a.ustride * 4;
   for (int i = lane; i < 4 * a.ustride; i += 64) acc[i] = 0.0;
   wave_lds_sync();
-  const int c = lane / kLanesPerCell, v = lane % kLanesPerCell;
+  const int c = lane / kLanesPerCell, v = lane % kLanesPerCell, g = v;
   const int cell = tile * kTile + c;
-  const bool live = cell < a.n_cell && v < 4;
+  const bool live = cell < a.n_cell;
   const int cl = live ? cell : tile * kTile;
   const unsigned nib = live ? ((a.flags[cl] >> (4 * v)) & 0xFu) : 0u;
   double gsum = 0.0;
@@ -1476,61 +1490,140 @@ __global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
 #pragma unroll
     for (int l = 0; l < NU; ++l) ab[l] = fma(FaceBasis<O::R, NQ>::P.v[q][l], gq, ab[l]);
   }
-  // entry (s, l) of this cell's stencil k (3 = large) in the tile's stream
-  // (the adjoint runs on meshes in conservative variables: dense)
+  // the tile's operator stream (dense: the adjoint runs on meshes in
+  // conservative variables)
   const double* __restrict__ mt =
       reinterpret_cast<const double*>(a.M) + (size_t)tile * O::template JPD<true> * kTile;
-  auto small_entry = [&](int k, int s, int l) {
-    return mt[(size_t)block_start(k, true) * kTile +
-              block_offset(kSmallRows, kSmallCoef, true, c, s, l)];
-  };
-  auto large_entry = [&](int s, int l) {
-    return mt[(size_t)block_start(3, true) * kTile + large_block_offset(O::NL, NU, true, c, s, l)];
-  };
   const uint16_t* __restrict__ sl =
       reinterpret_cast<const uint16_t*>(a.aslot + (size_t)tile * slot_int4(O::ROWS4));
   const int rounds = a.tround[tile];  // >= 1, the same for the whole wavefront
-  // row r's difference adjoint d into its member's accumulator, in its round
+  auto slot_of = [&](int r) { return (int)sl[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)]; };
+  // adds d into accumulator column q of the row's member, in the row's round
   // (the first round unconditionally, so the slot word is loaded with the
   // row's operator entries rather than after them)
-  auto add_row = [&](int r, double d) {
-    const int w = sl[(r >> 2) * (kTile * 4) + c * 4 + (r & 3)];
-    double* dst = &acc[(w & 511) * 4 + v];
+  auto add_in_round = [&](int w, int q, double d, bool on) {
+    double* dst = &acc[(w & 511) * 4 + q];
     const int mine = w >> 9;
-    int q = 0;
+    int r = 0;
     do {
-      if (mine == q) atomicAdd(dst, d);
-    } while (++q < rounds);
+      if (on && mine == r) atomicAdd(dst, d);
+    } while (++r < rounds);
   };
   const bool keepK = nib & 8u;
   const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
-  double dsum = 0.0;
-  // small stencils: coefficient adjoint ab[l]/cnt when kept in step two
+  // the flags of the cell's four variables, on all four lanes
+  unsigned nq[4];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const bool kept = live && !keepK && (nib & (1u << k)) && cnt > 0;
-    if (kept) {
-      const double wk = 1.0 / (double)cnt;
+  for (int q = 0; q < 4; ++q) nq[q] = quad_bcast_u(nib, q);
+  // weight of stencil k (3 = large) for variable q: a small stencil counts
+  // 1/cnt where step two kept it, the large one 1 where step one kept it
+  auto weight = [&](int k, int q) {
+    const unsigned f = nq[q];
+    if (!live) return 0.0;
+    if (k == 3) return (f & 8u) ? 1.0 : 0.0;
+    const int cq = (int)(f & 1u) + (int)((f >> 1) & 1u) + (int)((f >> 2) & 1u);
+    return (!(f & 8u) && ((f >> k) & 1u) && cq > 0) ? 1.0 / (double)cq : 0.0;
+  };
+  double dsum = 0.0;                    // rows read by variable (lane v)
+  double dq[4] = {0.0, 0.0, 0.0, 0.0};  // rows read by lane: this lane's rows, per variable
+
+  // rows by lane: a block of NR rows of L entries at block k of the stream,
+  // with coefficient adjoints ab4 of all four variables and weights w
+  auto lane_block = [&](auto kc, auto nrc, auto lc, const auto& ab4) {
+    constexpr int K = decltype(kc)::value, NR = decltype(nrc)::value, L = decltype(lc)::value;
+    constexpr int R0 = K == 3 ? 33 : kSmallRows * K;
+    const double w[4] = {weight(K, 0), weight(K, 1), weight(K, 2), weight(K, 3)};
+    const bool need = (w[0] != 0.0) | (w[1] != 0.0) | (w[2] != 0.0) | (w[3] != 0.0);
+    if (!__any(need)) return;
+    const double* __restrict__ mb = mt + (size_t)block_start(K, true) * kTile;
+    static_for<0, (NR + 3) / 4>([&](auto jc) {
+      constexpr int J = jc, rg = group_rows(NR, J);
+      const int gg = g < rg ? g : rg - 1;
+      const bool on = g < rg;
+      const int s = 4 * J + gg;
+      double m[L];
 #pragma unroll
-      for (int s = 0; s < 11; ++s) {
-        double d = 0.0;
+      for (int l = 0; l < L; ++l) m[l] = mb[4 * kTile * L * J + (l * kTile + c) * rg + gg];
+      const int w0 = slot_of(R0 + s);
 #pragma unroll
-        for (int l = 0; l < 5; ++l) d = fma(small_entry(k, s, l), ab[l], d);
-        d *= wk;
-        dsum += d;
-        add_row(small_row(k, s), d);
+      for (int q = 0; q < 4; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) t = fma(m[l], ab4[l][q], t);
+        const double d = (on && w[q] != 0.0) ? t * w[q] : 0.0;
+        dq[q] += d;
+        add_in_round(w0, q, d, on && w[q] != 0.0);
+      }
+    });
+  };
+
+  // ---- small stencils ----
+  if constexpr (SL) {
+    double ab4[kSmallCoef][4];
+#pragma unroll
+    for (int l = 0; l < kSmallCoef; ++l) {
+      ab4[l][0] = quad_bcast<0>(ab[l]);
+      ab4[l][1] = quad_bcast<1>(ab[l]);
+      ab4[l][2] = quad_bcast<2>(ab[l]);
+      ab4[l][3] = quad_bcast<3>(ab[l]);
+    }
+    using I = std::integral_constant<int, kSmallRows>;
+    using C = std::integral_constant<int, kSmallCoef>;
+    lane_block(std::integral_constant<int, 0>{}, I{}, C{}, ab4);
+    lane_block(std::integral_constant<int, 1>{}, I{}, C{}, ab4);
+    lane_block(std::integral_constant<int, 2>{}, I{}, C{}, ab4);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const bool kept = live && !keepK && (nib & (1u << k)) && cnt > 0;
+      if (kept) {
+        const double wk = 1.0 / (double)cnt;
+#pragma unroll
+        for (int s = 0; s < kSmallRows; ++s) {
+          double d = 0.0;
+#pragma unroll
+          for (int l = 0; l < kSmallCoef; ++l)
+            d = fma(mt[(size_t)block_start(k, true) * kTile + block_offset(kSmallRows, kSmallCoef, true, c, s, l)],
+                    ab[l], d);
+          d *= wk;
+          dsum += d;
+          add_in_round(slot_of(small_row(k, s)), v, d, true);
+        }
       }
     }
   }
-  if (live && keepK) {
+  // ---- large stencil ----
+  if constexpr (LL) {
+    double ab4[NU][4];
+#pragma unroll
+    for (int l = 0; l < NU; ++l) {
+      ab4[l][0] = quad_bcast<0>(ab[l]);
+      ab4[l][1] = quad_bcast<1>(ab[l]);
+      ab4[l][2] = quad_bcast<2>(ab[l]);
+      ab4[l][3] = quad_bcast<3>(ab[l]);
+    }
+    lane_block(std::integral_constant<int, 3>{}, std::integral_constant<int, O::NL>{},
+               std::integral_constant<int, NU>{}, ab4);
+  } else if (live && keepK) {
 #pragma unroll 1
     for (int s = 0; s < O::NL; ++s) {
       double d = 0.0;
 #pragma unroll
-      for (int l = 0; l < NU; ++l) d = fma(large_entry(s, l), ab[l], d);
+      for (int l = 0; l < NU; ++l)
+        d = fma(mt[(size_t)block_start(3, true) * kTile + large_block_offset(O::NL, NU, true, c, s, l)],
+                ab[l], d);
       dsum += d;
-      add_row(large_row(s), d);
+      add_in_round(slot_of(large_row(s)), v, d, true);
     }
+  }
+  // the rows read by lane: variable v's sum over the cell's four lanes
+  if constexpr (SL || LL) {
+    const bool odd = lane & 1, hi = lane & 2;
+    const double k0 = odd ? dq[1] : dq[0], k1 = odd ? dq[3] : dq[2];
+    const double s0 = odd ? dq[0] : dq[1], s1 = odd ? dq[2] : dq[3];
+    const double p0 = k0 + quad_perm_dpp<0xB1>(s0), p1 = k1 + quad_perm_dpp<0xB1>(s1);
+    const double keep = hi ? p1 : p0, send = hi ? p0 : p1;
+    dsum = (keep + quad_perm_dpp<0x4E>(send)) + dsum;
   }
   if (live) a.own[(size_t)cell * 4 + v] = gsum - dsum;
   wave_lds_sync();

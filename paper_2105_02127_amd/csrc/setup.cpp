@@ -713,19 +713,32 @@ int mesh_setup(Mesh& m, const teno_params& p) {
           m.slot[k] = (uint16_t)(std::lower_bound(u.begin(), u.end(), m.idx[k]) - u.begin());
         }
       }
-      // rounds of the adjoint's per-row additions: cells of the tile that
-      // name the same member in the same row add in cell order, one round
-      // each, so no two lanes of one LDS instruction hit the same address
+      // rounds of the adjoint's additions, so that no two lanes of one LDS
+      // instruction hit the same address: a block stored rows by lane adds
+      // four rows of every cell at once (rows 4j..4j+3 of the block, lane
+      // order c * 4 + g), and the lanes of such a group that name the same
+      // member add in lane order, one round each; a block of entry pairs
+      // adds one row at a time, and the cells that name the same member in
+      // that row add in cell order
       int top = 1;
-      for (int r = 0; r < d.rows; ++r)
-        for (int c = 0; c < kTile && tile * kTile + c < nc; ++c) {
-          const int64_t k = packed_idx_index(m, tile * kTile + c, r);
-          int q = 0;
-          for (int c2 = 0; c2 < c; ++c2)
-            if (m.slot[packed_idx_index(m, tile * kTile + c2, r)] == m.slot[k]) ++q;
-          m.aslot[k] = (uint16_t)(m.slot[k] | q << 9);
-          top = std::max(top, q + 1);
+      auto rounds = [&](int r0, int nrow, bool by_lane) {
+        const int span = by_lane ? 4 : 1;
+        for (int j = 0; j * span < nrow; ++j) {
+          const int rg = std::min(span, nrow - j * span);
+          for (int c = 0; c < kTile && tile * kTile + c < nc; ++c)
+            for (int gq = 0; gq < rg; ++gq) {
+              const int64_t k = packed_idx_index(m, tile * kTile + c, r0 + j * span + gq);
+              int q = 0;
+              for (int c2 = 0; c2 <= c; ++c2)
+                for (int g2 = 0; g2 < rg && (c2 < c || g2 < gq); ++g2)
+                  if (m.slot[packed_idx_index(m, tile * kTile + c2, r0 + j * span + g2)] == m.slot[k]) ++q;
+              m.aslot[k] = (uint16_t)(m.slot[k] | q << 9);
+              top = std::max(top, q + 1);
+            }
         }
+      };
+      for (int k = 0; k < 3; ++k) rounds(small_row(k, 0), kSmallRows, lane_rows(kSmallCoef, d.dense));
+      rounds(large_row(0), d.nl, large_lane_rows(d.nu, d.dense));
       m.tround[tile] = top;
     });
     if (umax.load() > kMaxTileMembers)
