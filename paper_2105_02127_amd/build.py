@@ -46,8 +46,8 @@ def build(verbose: bool = False, resource_usage: bool = False, lib: str = LIB,
     _run(["hipcc", *HIP_FLAGS, *extra_hip, *extra, "-c", os.path.join(CSRC, "teno_api.hip"), "-o",
           api_o], verbose)
     # the tetrahedral path: a translation unit of its own
-    _run(["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, "teno3_api.hip"), "-o", api3_o],
-         verbose)
+    _run(["hipcc", *HIP_FLAGS, *extra_hip, *extra, "-c", os.path.join(CSRC, "teno3_api.hip"), "-o",
+          api3_o], verbose)
     tmp = lib + ".tmp"
     _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
           setup_o, setup3_o, api_o, api3_o, "-pthread",

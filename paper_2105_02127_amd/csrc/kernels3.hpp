@@ -100,31 +100,125 @@ __device__ __forceinline__ double qform3(const double* T, const double (&x)[N]) 
   return s;
 }
 
-// Least squares of one stencil for lane variable v (Sec. 2.2 eqs. 08-10):
-// acc = M d, d_s = U_member(s) - U_0, rows streamed in order; the member
-// state of the next row is loaded while the current row is accumulated.
-template <int ROWS, int JP, int NC, int RS>
-__device__ __forceinline__ void gemv3(const Recon3Args& a, int tile, int c, int v, int nr,
-                                      int row0, int j0, double u0, double (&acc)[NC]) {
-  const int32_t* __restrict__ ip = a.idx + ((size_t)tile * ROWS + row0) * kTile3 + c;
-  const double2* __restrict__ mp = a.M + ((size_t)tile * (JP / 2) + j0 / 2) * kTile3 + c;
+// Least squares of one stencil (Sec. 2.2 eqs. 08-10), a = M d with
+// d_s = U_member(s) - U_0, for all five variables at once.  The five lanes
+// of a cell split the row's entry pairs (lane g takes pairs g, g + 5, ...)
+// so every operator byte is loaded by one lane only; each lane gathers all
+// five variables of the row's member and accumulates acc[t][k][v] for its
+// pairs.  Lanes past the row's last pair re-read that pair (the loads stay
+// unconditional) and their sums are never read.  NB rows are in flight.
+// Least squares of one stencil (Sec. 2.2 eqs. 08-10), a = M d with
+// d_s = U_member(s) - U_0, for all five variables at once.  The five lanes
+// of a cell split the row's entry pairs (lane g takes pairs g, g + 5, ...)
+// so every operator byte is loaded by one lane only.  Lane g gathers
+// variable g of the row's member (its id read from the tile's rows staged
+// in LDS, so the gather never waits behind the operator loads) and the five
+// lanes share the five values by lane shuffles; each lane accumulates
+// acc[t][k][v] for its pairs.  Lanes past the row's last pair re-read that
+// pair (the loads stay unconditional) and their sums are never read.  NB
+// rows live in fixed buffers and the loop is unrolled by NB: while one row
+// is accumulated the next NB - 1 are in flight.
+template <int NR, int RS, int NB>
+struct Stream3 {
+  static constexpr int NPAIR = RS / 2;
+  static constexpr int NT = (NPAIR + kVars3 - 1) / kVars3;
+  using Acc = double[NT][2][kVars3];
+  typedef double v2d __attribute__((ext_vector_type(2)));
+
+  const int32_t* sid;              // LDS: member ids of this stencil's rows, [row][kTile3]
+  const double2* __restrict__ mp;  // this cell's pairs of row 0 (stride kTile3)
+  const double* __restrict__ U;
+  int c, g;
+  double u0[kVars3];
+  double xq[NB];
+  v2d mq[NB][NT];
+
+  __device__ __forceinline__ int pair_of(int t) const {
+    const int p = g + kVars3 * t;
+    return p < NPAIR ? p : NPAIR - 1;
+  }
+  __device__ __forceinline__ void issue(int s, double& x, v2d (&m)[NT]) const {
+    s = s < NR ? s : NR - 1;  // loads past the last row re-read it (never used)
+    const int id = sid[s * kTile3 + c];
+    x = U[(size_t)id * kVars3 + g];
+    const double2* __restrict__ mr = mp + (size_t)s * NPAIR * kTile3;
 #pragma unroll
-  for (int l = 0; l < NC; ++l) acc[l] = 0.0;
-  double x = a.U[(size_t)ip[0] * kVars3 + v];
+    for (int t = 0; t < NT; ++t)
+      m[t] = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(&mr[(size_t)pair_of(t) * kTile3]));
+  }
+  __device__ __forceinline__ void accumulate(double x, const v2d (&m)[NT], Acc& acc) const {
+    const int b = kVars3 * c;
+    double d[kVars3];
+#pragma unroll
+    for (int v = 0; v < kVars3; ++v) d[v] = __shfl(x, b + v) - u0[v];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < kVars3; ++v) {
+        acc[t][0][v] = fma(m[t].x, d[v], acc[t][0][v]);
+        acc[t][1][v] = fma(m[t].y, d[v], acc[t][1][v]);
+      }
+  }
+  __device__ __forceinline__ void run(Acc& acc) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < kVars3; ++v) acc[t][0][v] = acc[t][1][v] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NB - 1; ++k) issue(k, xq[k], mq[k]);
+    int s = 0;
 #pragma unroll 1
-  for (int s = 0; s < nr; ++s) {
-    const int sn = s + 1 < nr ? s + 1 : s;
-    const double xn = a.U[(size_t)ip[(size_t)sn * kTile3] * kVars3 + v];
-    const double d = x - u0;
-    const double2* __restrict__ mr = mp + (size_t)(s * (RS / 2)) * kTile3;
+    for (; s + NB - 1 < NR; s += NB) {
 #pragma unroll
-    for (int q = 0; q < RS / 2; ++q) {
-      typedef double v2d __attribute__((ext_vector_type(2)));
-      const v2d m = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(&mr[(size_t)q * kTile3]));
-      acc[2 * q] = fma(m.x, d, acc[2 * q]);
-      if (2 * q + 1 < NC) acc[2 * q + 1] = fma(m.y, d, acc[2 * q + 1]);
+      for (int k = 0; k < NB; ++k) {
+        const int nb = (k + NB - 1) % NB;
+        issue(s + k + NB - 1, xq[nb], mq[nb]);
+        accumulate(xq[k], mq[k], acc);
+      }
     }
-    x = xn;
+#pragma unroll
+    for (int k = 0; k < NB - 1; ++k)
+      if (s + k < NR) accumulate(xq[k], mq[k], acc);
+  }
+};
+
+// rows in flight: the small streams have one pair per lane and row, so more
+// of their rows fit in registers than of the large ones
+#ifndef TENO3_SMALL_BUFFERS
+#define TENO3_SMALL_BUFFERS 4
+#endif
+#ifndef TENO3_LARGE_BUFFERS
+#define TENO3_LARGE_BUFFERS 3
+#endif
+
+// Hands lane (c, v) variable v's coefficients from the split sums: every
+// lane writes its pairs' sums for all variables to the wave's scratch, one
+// pair slot t at a time, and reads back the variable it owns.  Lanes 60-63
+// (no cell) write nothing.
+template <int NT, int NC>
+__device__ __forceinline__ void transpose3(const double (&acc)[NT][2][kVars3], double* sc, int lane,
+                                           int c, int g, double (&co)[NC]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (lane < 60) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int v = 0; v < kVars3; ++v) sc[((c * kVars3 + g) * 2 + k) * kVars3 + v] = acc[t][k][v];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int h = 0; h < kVars3; ++h)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int l = 2 * (h + kVars3 * t) + k;
+        if (l < NC) co[l] = sc[((c * kVars3 + h) * 2 + k) * kVars3 + g];
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -135,20 +229,34 @@ __device__ __forceinline__ bool physical3(double r, double mx, double my, double
   return p > 0.0;  // false for NaN
 }
 
-// Reconstruction of one tile (12 cells, lane = 5 c + v) in four passes that
-// keep few coefficient vectors live: the indicators of the four small
-// stencils (their coefficients are dropped), the large stencil's
-// coefficients and indicator, the selection of Sec. 3.3 with K = 4, and -
-// only where the large stencil is rejected - the coefficients of the kept
-// small stencils again, averaged.  Face values of the selected polynomial are
-// written as they are formed.
+// Reconstruction of one tile (12 cells; lane 5c + g): the least-squares
+// streams split each row's pairs over the cell's five lanes (all variables
+// per lane), and a transpose through LDS gives lane g the coefficients of
+// variable g for the selection of Sec. 3.3 with K = 4.  The small stencils'
+// indicators come first (their coefficients are dropped), then the large
+// stencil's coefficients and indicator, the selection, and - only where a
+// variable of the wavefront rejects the large stencil - the small stencils
+// again, averaged over the kept ones.  Face values of the selected
+// polynomial are written as they are formed.
 template <int P>
 __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   using O = O3<P>;
   constexpr int NU = O::NU, NPT = O::NPT, NP = 4 * NPT;
   constexpr int NPSI = NP * NU, NBL = packed3<NU>(), NBS = packed3<kSmall3Coef>();
+  constexpr int NSC = kTile3 * kVars3 * 2 * kVars3;  // one pair slot of every lane
+  constexpr int NID = O::ROWS * kTile3;                // the tile's member ids
   __shared__ double tab[NPSI + NBL + NBS];
+  __shared__ double scratch[4][NSC];
+  __shared__ int32_t ids[4][NID];
   for (int i = threadIdx.x; i < NPSI + NBL + NBS; i += 256) tab[i] = a.tab[i];
+  {
+    const int w = threadIdx.x >> 6;
+    const int t = xcd_remap3(blockIdx.x, gridDim.x) * 4 + w;
+    if (t < a.n_tiles) {
+      const int32_t* __restrict__ src = a.idx + (size_t)t * NID;
+      for (int i = threadIdx.x & 63; i < NID; i += 64) ids[w][i] = src[i];
+    }
+  }
   __syncthreads();
   const double* psi = tab;
   const double* Bl = tab + NPSI;
@@ -156,17 +264,41 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tile = __builtin_amdgcn_readfirstlane(xcd_remap3(blockIdx.x, gridDim.x) * 4 + wave);
-  if (tile >= a.n_tiles) return;  // whole wavefront leaves together; no barrier follows
+  if (tile >= a.n_tiles) return;  // whole wavefront leaves together; only wave barriers follow
+  double* sc = scratch[wave];
   const int c = lane < 60 ? lane / kVars3 : kTile3 - 1;
-  const int v = lane < 60 ? lane - kVars3 * c : 0;
+  const int g = lane < 60 ? lane - kVars3 * c : 0;
+  const int v = g;
   const int cell = tile * kTile3 + c;
   const bool live = lane < 60 && cell < a.n_cell;
   const int cl = cell < a.n_cell ? cell : tile * kTile3;
-  const double u0 = a.U[(size_t)cl * kVars3 + v];
+  double u0[kVars3];
+#pragma unroll
+  for (int q = 0; q < kVars3; ++q) u0[q] = a.U[(size_t)cl * kVars3 + q];
+  const double u0v = u0[v];
+
+  using SmallS = Stream3<kSmall3Rows, kSmall3Stored, TENO3_SMALL_BUFFERS>;
+  using LargeS = Stream3<O::NL, O::RSL, TENO3_LARGE_BUFFERS>;
+  const int32_t* tid = ids[wave];
+  auto small_stream = [&](int k) {
+    SmallS st{tid + k * kSmall3Rows * kTile3,
+              a.M + ((size_t)tile * (O::JP / 2) + k * kSmall3Blk / 2) * kTile3 + c, a.U, c, g};
+#pragma unroll
+    for (int q = 0; q < kVars3; ++q) st.u0[q] = u0[q];
+    return st;
+  };
 
   // ---- large stencil ----
   double co[NU];
-  gemv3<O::ROWS, O::JP, NU, O::RSL>(a, tile, c, v, O::NL, 4 * kSmall3Rows, 4 * kSmall3Blk, u0, co);
+  {
+    LargeS st{tid + 4 * kSmall3Rows * kTile3,
+              a.M + ((size_t)tile * (O::JP / 2) + 4 * kSmall3Blk / 2) * kTile3 + c, a.U, c, g};
+#pragma unroll
+    for (int q = 0; q < kVars3; ++q) st.u0[q] = u0[q];
+    typename LargeS::Acc acc;
+    st.run(acc);
+    transpose3<LargeS::NT, NU>(acc, sc, lane, c, g, co);
+  }
   // ---- selection (Sec. 3.2-3.3, K = 4); the linear scheme keeps the large
   // stencil and never reads the small ones.  Each indicator is formed in the
   // block that uses it, so that its table reads are not hoisted apart from
@@ -174,19 +306,21 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   unsigned nib = 0x10u;
   int ties = 0;
   if (a.variant == 0) {
-    double g[4], gs = 0.0;
+    double gk[4], gs = 0.0;
 #pragma unroll 1
     for (int k = 0; k < 4; ++k) {
+      SmallS st = small_stream(k);
+      typename SmallS::Acc acc;
+      st.run(acc);
       double as[kSmall3Coef];
-      gemv3<O::ROWS, O::JP, kSmall3Coef, kSmall3Stored>(a, tile, c, v, kSmall3Rows,
-                                                        k * kSmall3Rows, k * kSmall3Blk, u0, as);
-      const double gk = gamma3(qform3<kSmall3Coef>(Bs, as), a.eps, a.power);
+      transpose3<SmallS::NT, kSmall3Coef>(acc, sc, lane, c, g, as);
+      const double gam = gamma3(qform3<kSmall3Coef>(Bs, as), a.eps, a.power);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (q == k) g[q] = gk;
+        if (q == k) gk[q] = gam;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) gs += g[k];
+    for (int k = 0; k < 4; ++k) gs += gk[k];
     const double gK = gamma3(qform3<NU>(Bl, co), a.eps, a.power);
     const double chiK = gK / (gs + gK);
     ties += tie3(a, chiK);
@@ -195,31 +329,37 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
       const double is = 1.0 / gs;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double x = g[k] * is;
+        const double x = gk[k] * is;
         ties += tie3(a, x);
         if (x >= a.ct) nib |= 1u << k;
       }
     }
   }
-  // ---- large stencil rejected: the mean of the kept small stencils ----
-  if (!(nib & 0x10u)) {
+  // ---- large stencil rejected: the mean of the kept small stencils (the
+  // streams run for the whole wavefront; each lane takes what it keeps) ----
+  if (__any(!(nib & 0x10u))) {
     double ab[kSmall3Coef];
 #pragma unroll
     for (int l = 0; l < kSmall3Coef; ++l) ab[l] = 0.0;
     int cnt = 0;
 #pragma unroll 1
     for (int k = 0; k < 4; ++k) {
-      if (!((nib >> k) & 1u)) continue;
+      SmallS st = small_stream(k);
+      typename SmallS::Acc acc;
+      st.run(acc);
       double as[kSmall3Coef];
-      gemv3<O::ROWS, O::JP, kSmall3Coef, kSmall3Stored>(a, tile, c, v, kSmall3Rows,
-                                                        k * kSmall3Rows, k * kSmall3Blk, u0, as);
+      transpose3<SmallS::NT, kSmall3Coef>(acc, sc, lane, c, g, as);
+      if (!(nib & 0x10u) && ((nib >> k) & 1u)) {
 #pragma unroll
-      for (int l = 0; l < kSmall3Coef; ++l) ab[l] += as[l];
-      ++cnt;
+        for (int l = 0; l < kSmall3Coef; ++l) ab[l] += as[l];
+        ++cnt;
+      }
     }
     // the small stencils' basis is the first nine functions of the large one
+    if (!(nib & 0x10u)) {
 #pragma unroll
-    for (int l = 0; l < NU; ++l) co[l] = (l < kSmall3Coef && cnt > 0) ? ab[l] / (double)cnt : 0.0;
+      for (int l = 0; l < NU; ++l) co[l] = (l < kSmall3Coef && cnt > 0) ? ab[l] / (double)cnt : 0.0;
+    }
   }
   // ---- face values, written as formed; the five lanes of a cell share
   // their values for the physical-state test ----
@@ -229,7 +369,7 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   const size_t qstride = (size_t)a.n_pad * kVars3;
 #pragma unroll 1
   for (int q = 0; q < NP; ++q) {
-    double s = u0;
+    double s = u0v;
     int o = q * NU;
 #pragma unroll
     for (int l = 0; l < NU; ++l) {
@@ -240,15 +380,14 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
                       __shfl(s, b0 + 4), a.gamma) && fp_ok;
     if (live) out[q * qstride] = s;
   }
-  const bool avg_ok = physical3(__shfl(u0, b0), __shfl(u0, b0 + 1), __shfl(u0, b0 + 2),
-                                __shfl(u0, b0 + 3), __shfl(u0, b0 + 4), a.gamma);
+  const bool avg_ok = physical3(u0[0], u0[1], u0[2], u0[3], u0[4], a.gamma);
   if (live && v == 0 && !(avg_ok && fp_ok)) {
     atomicAdd(&a.diag->nonphysical, 1ull);
     atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
   }
   if (!fp_ok && avg_ok && a.fallback) {
     if (live) {
-      for (int q = 0; q < NP; ++q) out[q * qstride] = u0;
+      for (int q = 0; q < NP; ++q) out[q * qstride] = u0v;
       if (v == 0) atomicAdd(&a.diag->fallbacks, 1ull);
     }
     nib = 0u;
