@@ -280,8 +280,17 @@ __device__ __forceinline__ int near_tie(const ReconArgs& a, double chi) {
 
 __device__ __forceinline__ double gamma_k(double beta, double eps, int power) {
   const double x = beta + eps;
-  double xp = 1.0;
-  for (int t = 0; t < power; ++t) xp *= x;
+  double xp;
+  if (power == 6) {  // the paper's q: the same products, in the same order, unrolled
+    xp = x * x;
+    xp *= x;
+    xp *= x;
+    xp *= x;
+    xp *= x;
+  } else {
+    xp = 1.0;
+    for (int t = 0; t < power; ++t) xp *= x;
+  }
   return 1.0 / xp;
 }
 
@@ -895,6 +904,246 @@ __device__ __forceinline__ void char_edges(const ReconArgs& a, const double (&as
 // this wavefront's LDS area (stage_int4(ROWS4, a.ustride) int4).  CW selects the
 // CWENO weighting (Sec. 2.4) instead of the TENO selection (Sec. 3); CH
 // selects in characteristic variables, edge by edge (Sec. 2.3).
+#ifndef TENO_CHAR_GRAM
+#define TENO_CHAR_GRAM 1
+#endif
+// Characteristic TENO (and Linear) without projecting the coefficients for
+// the indicators.  For each stencil the Gram matrix G = sum_lm B_lm a_l a_m^T
+// of the four variables' coefficient vectors (4 x 4, symmetric) is formed
+// once per cell; the indicator of characteristic variable v on an edge is
+// then L_v^T G L_v, which equals beta of the projected coefficients L_v a.
+// The selection follows per variable.  Where the four variables of a cell
+// select alike on an edge (every smooth cell, and any jump that all fields
+// see), the projection cancels (R L = I) and the face states are the
+// conservative combination of the same stencils; only cells whose fields
+// select differently project the coefficients and map back, as in
+// char_edges.  The Gram matrices live in the wave's staging LDS (16 cells x
+// 4 stencils x 10 entries), which the least-squares phase no longer needs.
+constexpr int kCharGramDoubles = kTile * 4 * 10;
+__host__ __device__ constexpr int char_gram_int4() { return kCharGramDoubles * 8 / 16; }
+
+__device__ __forceinline__ int gram_off(int i, int j) {  // i <= j
+  return i * 4 - (i * (i - 1)) / 2 + (j - i);
+}
+
+// Row v of the Gram matrix of one stencil, G_vj = (a^j)^T B a^v, from the
+// factor B = L D L^T: with z = L^T a, G_vj = sum_l d_l z^v_l z^j_l.  One
+// component of z at a time; the empty asm ties each step to the previous
+// step's sums so that the compiler does not form all of z up front.
+template <int R>
+__device__ __forceinline__ void gram_rows(const double* a, int v, double* G) {
+  using S = SmoothForm<R>;
+  constexpr int N = S::N;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    double z = a[l];
+    asm volatile("" : "+v"(z), "+v"(r0), "+v"(r1), "+v"(r2), "+v"(r3));
+#pragma unroll
+    for (int m = l + 1; m < N; ++m) z = fma(S::LDL.Lt[l][m], a[m], z);
+    const double w = S::LDL.d[l] * z;
+    r0 = fma(quad_bcast<0>(z), w, r0);
+    r1 = fma(quad_bcast<1>(z), w, r1);
+    r2 = fma(quad_bcast<2>(z), w, r2);
+    r3 = fma(quad_bcast<3>(z), w, r3);
+  }
+  const double r[4] = {r0, r1, r2, r3};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j >= v) G[gram_off(v, j)] = r[j];
+}
+
+// Row v of the left eigenvector matrix for edge normal (nx, ny), formed
+// directly for the lane's own variable: with
+//   A = (b2, -b1 ux, -b1 uy, b1), B = (un, -nx, -ny, 0) / c, C = (-ut, -ny, nx, 0)
+// the rows are A/2 + B/2 (v = 0), (1, 0, 0, 0) - A (v = 1), C (v = 2) and
+// A/2 - B/2 (v = 3), the same matrix as char_lrow.
+__device__ __forceinline__ void char_lrow_lane(const CharState& S, double nx, double ny, bool ok,
+                                               int v, double (&lrow)[4]) {
+  const double un = S.ux * nx + S.uy * ny, ut = S.uy * nx - S.ux * ny;
+  const double ca = v == 1 ? -1.0 : (v == 2 ? 0.0 : 0.5);
+  const double cb = v == 0 ? 0.5 : (v == 3 ? -0.5 : 0.0);
+  const double cc = v == 2 ? 1.0 : 0.0;
+  const double cd = v == 1 ? 1.0 : 0.0;
+  const double A[4] = {S.b2, -S.b1 * S.ux, -S.b1 * S.uy, S.b1};
+  const double B[4] = {un * S.ic, -nx * S.ic, -ny * S.ic, 0.0};
+  const double Cv[4] = {-ut, -ny, nx, 0.0};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double r = fma(ca, A[j], fma(cb, B[j], cc * Cv[j])) + (j == 0 ? cd : 0.0);
+    lrow[j] = ok ? r : (j == v ? 1.0 : 0.0);
+  }
+}
+
+// The ten products of a row L that pair with the stored entries of G
+// (diagonal once, off-diagonal doubled), in gram_off order.
+__device__ __forceinline__ void gram_weights(const double (&L)[4], double (&q)[10]) {
+  const double t0 = L[0] + L[0], t1 = L[1] + L[1], t2 = L[2] + L[2];
+  q[0] = L[0] * L[0];
+  q[1] = t0 * L[1];
+  q[2] = t0 * L[2];
+  q[3] = t0 * L[3];
+  q[4] = L[1] * L[1];
+  q[5] = t1 * L[2];
+  q[6] = t1 * L[3];
+  q[7] = L[2] * L[2];
+  q[8] = t2 * L[3];
+  q[9] = L[3] * L[3];
+}
+
+__device__ __forceinline__ double gram_dot(const double* G, const double (&q)[10]) {
+  double s = q[0] * G[0];
+#pragma unroll
+  for (int k = 1; k < 10; ++k) s = fma(q[k], G[k], s);
+  return s;
+}
+
+template <int P, int NQ>
+__device__ __forceinline__ void char_edges_gram(const ReconArgs& a, const double (&as)[3][5],
+                                                const double (&aK)[OrderT<P>::NU], double u0,
+                                                int cell, bool live, bool writer, int g, int v,
+                                                int c, int4* stage) {
+  using O = OrderT<P>;
+  constexpr int NU = O::NU;
+  const bool avg_ok = physical(quad_bcast<0>(u0), quad_bcast<1>(u0), quad_bcast<2>(u0),
+                               quad_bcast<3>(u0), a.gamma);
+  const double* __restrict__ gc = a.geo + (size_t)(live ? cell : 0) * 10;
+  const int side = a.nbinfo[live ? cell : 0].w;  // face normals point out of the L side
+  // ---- Gram matrices of the four stencils (the staging LDS is free now) ----
+  double* gram = reinterpret_cast<double*>(stage) + c * 40;
+  wave_lds_sync();
+  if (a.variant == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gram_rows<2>(as[k], v, gram + 10 * k);
+  }
+  gram_rows<O::R>(aK, v, gram + 30);
+  wave_lds_sync();
+  int ties = 0;
+  bool fp_ok = true;
+  const CharCore core = char_core(char_state(u0, a.gamma));
+  auto state = [&]() { return char_expand(core, a.gamma); };
+  static_for<0, 3>([&](auto E) {
+    constexpr int e = E;
+    __builtin_amdgcn_sched_barrier(0);
+    const double sg = ((side >> (6 + e)) & 1) ? 1.0 : -1.0;
+    const double nx = sg * gc[3 * e], ny = sg * gc[3 * e + 1];
+    double lrow[4];
+    char_lrow_lane(state(), nx, ny, avg_ok, v, lrow);
+    // ---- selection of characteristic variable v (Sec. 3.2-3.3) ----
+    unsigned nib = 8u;
+    if (a.variant == 0) {
+      // an opaque offset per edge keeps the 40 Gram entries from being read
+      // once and held in registers across the three edges
+      int goff = c * 40;
+      asm volatile("" : "+v"(goff));
+      const double* gram = reinterpret_cast<const double*>(stage) + goff;
+      double q[10];
+      gram_weights(lrow, q);
+      const double g0 = gamma_k(gram_dot(gram, q), a.eps, a.power);
+      const double g1 = gamma_k(gram_dot(gram + 10, q), a.eps, a.power);
+      const double g2 = gamma_k(gram_dot(gram + 20, q), a.eps, a.power);
+      const double ssum = (g0 + g1) + g2;
+      const double is = 1.0 / ssum;
+      const double x0 = g0 * is, x1 = g1 * is, x2 = g2 * is;
+      const int st = near_tie(a, x0) + near_tie(a, x1) + near_tie(a, x2);
+      const unsigned nsm = (x0 >= a.ct ? 1u : 0u) | (x1 >= a.ct ? 2u : 0u) | (x2 >= a.ct ? 4u : 0u);
+      const double gK = gamma_k(gram_dot(gram + 30, q), a.eps, a.power);
+      const double chiK = gK / (ssum + gK);
+      ties += near_tie(a, chiK);
+      const bool keepK = chiK >= a.ct;
+      if (!keepK) ties += st;
+      nib = keepK ? 8u : nsm;
+    }
+    // ---- do the cell's four variables select alike? ----
+    const unsigned n0 = (unsigned)__builtin_amdgcn_mov_dpp((int)nib, 0x00, 0xF, 0xF, false);
+    const unsigned n1 = (unsigned)__builtin_amdgcn_mov_dpp((int)nib, 0x55, 0xF, 0xF, false);
+    const unsigned n2 = (unsigned)__builtin_amdgcn_mov_dpp((int)nib, 0xAA, 0xF, 0xF, false);
+    const unsigned n3 = (unsigned)__builtin_amdgcn_mov_dpp((int)nib, 0xFF, 0xF, 0xF, false);
+    const bool alike = n0 == n1 && n1 == n2 && n2 == n3;
+    const double* __restrict__ fb = &FaceBasis<O::R, NQ>::P.v[e * NQ][0];
+    // the combined coefficients one at a time, straight into the face sums
+    const int cnt = (int)(nib & 1u) + (int)((nib >> 1) & 1u) + (int)((nib >> 2) & 1u);
+    const double inv = cnt == 3 ? 1.0 / 3.0 : (cnt == 2 ? 0.5 : (cnt == 1 ? 1.0 : 0.0));
+    double val[NQ];
+    if (alike) {
+      // the conservative combination of the stencils every field selected
+#pragma unroll
+      for (int kq = 0; kq < NQ; ++kq) val[kq] = u0;
+#pragma unroll
+      for (int l = 0; l < NU; ++l) {
+        double ab = aK[l];
+        if (l < 5 && !(nib & 8u)) {
+          double sm = 0.0;
+          if (nib & 1u) sm += as[0][l];
+          if (nib & 2u) sm += as[1][l];
+          if (nib & 4u) sm += as[2][l];
+          ab = sm * inv;
+        } else if (!(nib & 8u)) {
+          ab = 0.0;
+        }
+#pragma unroll
+        for (int kq = 0; kq < NQ; ++kq) val[kq] = fma(ab, fb[kq * NU + l], val[kq]);
+      }
+    } else {
+      // fields select differently: project, combine per variable, map back
+      double dw[NQ];
+#pragma unroll
+      for (int kq = 0; kq < NQ; ++kq) dw[kq] = 0.0;
+#pragma unroll
+      for (int l = 0; l < NU; ++l) {
+        // every lane of the quad takes part in each projection (the four
+        // variables of a cell may select differently here)
+        double xk = aK[l];
+        asm volatile("" : "+v"(xk), "+v"(dw[0]), "+v"(dw[NQ - 1]));
+        const double wk = quad_dot(lrow, xk);
+        double ab = (nib & 8u) ? wk : 0.0;
+        if (l < 5) {
+          double x0 = as[0][l], x1 = as[1][l], x2 = as[2][l];
+          asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2) : "v"(wk));
+          const double w0 = quad_dot(lrow, x0), w1 = quad_dot(lrow, x1), w2 = quad_dot(lrow, x2);
+          double sm = 0.0;
+          if (nib & 1u) sm += w0;
+          if (nib & 2u) sm += w1;
+          if (nib & 4u) sm += w2;
+          if (!(nib & 8u)) ab = sm * inv;
+        }
+#pragma unroll
+        for (int kq = 0; kq < NQ; ++kq) dw[kq] = fma(ab, fb[kq * NU + l], dw[kq]);
+      }
+      double rrow[4];
+      char_rrow(state(), nx, ny, avg_ok, v, rrow);
+#pragma unroll
+      for (int kq = 0; kq < NQ; ++kq) val[kq] = u0 + quad_dot(rrow, dw[kq]);
+    }
+#pragma unroll
+    for (int kq = 0; kq < NQ; ++kq) {
+      fp_ok = fp_ok && physical(quad_bcast<0>(val[kq]), quad_bcast<1>(val[kq]),
+                                quad_bcast<2>(val[kq]), quad_bcast<3>(val[kq]), a.gamma);
+      if (live && writer) a.fp[((size_t)(e * NQ + kq) * a.n_pad + cell) * 4 + v] = val[kq];
+    }
+    if (a.flags) {  // one word per local edge: flags[e][n_cell]
+      unsigned f = nib << (4 * v);
+      f |= __shfl_xor(f, 1);
+      f |= __shfl_xor(f, 2);
+      if (live && g == 0) a.flags[(size_t)e * a.n_cell + cell] = (uint16_t)f;
+    }
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- non-physical states (all four lanes of a cell agree) ----
+  if (live && g == 0 && !(avg_ok && fp_ok)) {
+    atomicAdd(&a.diag->nonphysical, 1ull);
+    atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
+  }
+  if (!fp_ok && avg_ok && a.fallback) {
+    if (live && writer)
+      for (int q = 0; q < 3 * NQ; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + v] = u0;
+    if (a.flags && live && g == 0)
+      for (int e = 0; e < 3; ++e) a.flags[(size_t)e * a.n_cell + cell] = 0;
+    if (live && g == 0) atomicAdd(&a.diag->fallbacks, 1ull);
+  }
+  if (live && writer && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
+}
+
 template <int P, int NQ, bool CW = false, bool CH = false>
 __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, int lane,
                                                  int4* stage) {
@@ -1002,7 +1251,12 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
     static_for<0, NU>([&](auto L) { aK[L] = LargeS::template coef<L>(sk, v, lane); });
   }
   if constexpr (CH) {
-    char_edges<P, NQ, CW>(a, as, aK, u0, cell, live, writer, g, v);
+#if TENO_CHAR_GRAM
+    if constexpr (!CW)
+      char_edges_gram<P, NQ>(a, as, aK, u0, cell, live, writer, g, v, c, stage);
+    else
+#endif
+      char_edges<P, NQ, CW>(a, as, aK, u0, cell, live, writer, g, v);
     return;
   }
   int ties = 0;
@@ -1074,19 +1328,21 @@ void k_reconstruct(ReconArgs a) {
   reconstruct_tile<P, NQ, CW, false>(a, tile, lane, lds + wave * a.lds_stride);
 }
 
-// The same in characteristic variables.  The per-edge phase holds the
-// conservative and the projected coefficients at once; the register budget
-// is capped at TENO_CHAR_WAVES_PER_EU wavefronts per SIMD.
+// The same in characteristic variables.  The TENO kernel's register budget
+// is capped at TENO_CHAR_WAVES_PER_EU wavefronts per SIMD (left alone, the
+// order-6 kernel takes 175 VGPRs and two waves); the CWENO kernel, which
+// holds the projected coefficients of every stencil across its weights, is
+// left to the compiler.
 #ifndef TENO_CHAR_WAVES_PER_EU
-#define TENO_CHAR_WAVES_PER_EU 0
+#define TENO_CHAR_WAVES_PER_EU 3
 #endif
-#if TENO_CHAR_WAVES_PER_EU > 0
-#define TENO_CHAR_ATTR __attribute__((amdgpu_waves_per_eu(TENO_CHAR_WAVES_PER_EU)))
-#else
-#define TENO_CHAR_ATTR
-#endif
+template <bool CW>
+struct CharWaves {
+  static constexpr int value = (!CW && TENO_CHAR_WAVES_PER_EU > 0) ? TENO_CHAR_WAVES_PER_EU : 1;
+};
 template <int P, int NQ, bool CW>
-__global__ __launch_bounds__(256) TENO_CHAR_ATTR void k_reconstruct_char(ReconArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CharWaves<CW>::value)))
+void k_reconstruct_char(ReconArgs a) {
   extern __shared__ int4 lds[];  // 4 wavefronts x a.lds_stride
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;

@@ -88,6 +88,30 @@ struct SmoothForm {
     return M;
   }
   static constexpr Mat U = upper();
+  // B = L D L^T with L unit lower triangular (B is positive definite: the
+  // derivatives up to order R vanish together only for a constant, and the
+  // basis has zero mean).  Row l of Lt holds column l of L (Lt[l][m] = L_ml,
+  // m >= l) and d holds D, so that a^T B a = sum_l d_l (sum_{m>=l} Lt_lm a_m)^2.
+  struct Ldl {
+    double Lt[N][N] = {};
+    double d[N] = {};
+  };
+  static constexpr Ldl factor() {
+    Ldl f{};
+    for (int j = 0; j < N; ++j) {
+      double dj = B.v[j][j];
+      for (int k = 0; k < j; ++k) dj -= f.Lt[k][j] * f.Lt[k][j] * f.d[k];
+      f.d[j] = dj;
+      f.Lt[j][j] = 1.0;
+      for (int i = j + 1; i < N; ++i) {
+        double s = B.v[i][j];
+        for (int k = 0; k < j; ++k) s -= f.Lt[k][i] * f.Lt[k][j] * f.d[k];
+        f.Lt[j][i] = s / dj;
+      }
+    }
+    return f;
+  }
+  static constexpr Ldl LDL = factor();
 };
 
 // Gauss-Legendre points on [0,1] (t) and weights summing to one (w).

@@ -194,6 +194,7 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   a.tmem = s->tmem;
   a.ustride = s->ustride;
   a.lds_stride = stage_int4(s->d.rows4, s->ustride);
+  if (s->prm.characteristic != 0) a.lds_stride = std::max(a.lds_stride, char_gram_int4());
   a.M = s->M;
   a.fp = fp ? fp : s->fp;
   a.flags = flags;
