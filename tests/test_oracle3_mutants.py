@@ -59,6 +59,36 @@ MUTANTS = [
     ("wall_reflection", "uR[1 + a] = uL[1 + a] - 2.0 * mn * n[a];", "uR[1 + a] = uL[1 + a] - mn * n[a];"),
 ]
 
+# the pin expected to catch each mutant: it runs first, and the whole pin
+# suite only if it passes
+FIRST_PIN = {
+    "face_rule_weight": "test_face_rules_exact_and_symmetric",
+    "basis_mean_volume": "test_basis_graded_and_zero_mean",
+    "qr_reflector": "test_polynomial_reproduction",
+    "lsq_rhs_volume": "test_polynomial_reproduction",
+    "reference_volume": "test_polynomial_reproduction",
+    "member_unwrap": "test_polynomial_reproduction",
+    "inverse_map_row": "test_polynomial_reproduction",
+    "beta_multiplicity": "test_smoothness_closed_forms",
+    "gamma_power": "test_selection_threshold_and_step_two",
+    "cutoff_equality": "test_selection_threshold_and_step_two",
+    "step_two_normalisation": "test_selection_threshold_and_step_two",
+    "small_weights": "test_kept_small_stencils_are_averaged",
+    "cone_third_vertex": "test_stencil_cones_and_order",
+    "face_vertex_order": "test_geometry_closes_and_normals_point_out",
+    "reference_vertices": "test_polynomial_reproduction",
+    "face_point_pairing": "test_linear_field_residual_is_face_quadrature_of_exact_flux",
+    "hll_dissipation_sign": "test_hll3_resolves_isolated_shock",
+    "roe_weight": "test_hll3_resolves_isolated_shock",
+    "left_wave_speed": "test_hll3_antisymmetry_and_rotation",
+    "rotate_back_tangents": "test_hll3_consistency_and_upwinding",
+    "face_side_sign": "test_free_stream_and_conservation",
+    "residual_sign": "test_linear_field_residual_is_face_quadrature_of_exact_flux",
+    "dt_face_area": "test_dt_closed_form_on_a_cube",
+    "rk_stage_two": "test_rk3_is_third_order_in_time",
+    "wall_reflection": "test_closed_reflective_box_conserves_mass_and_energy",
+}
+
 
 def _run_mutant(tmp, name, old, new, src):
     assert src.count(old) == 1, f"mutation site of {name} not found exactly once"
@@ -72,7 +102,14 @@ def _run_mutant(tmp, name, old, new, src):
     cmd[cmd.index("-o") + 1] = lib
     cmd[-1] = cpp
     subprocess.run(cmd, check=True, capture_output=True)
-    env = dict(os.environ, ORACLE3_LIB=lib, OMP_NUM_THREADS="2")
+    env = dict(os.environ, ORACLE3_LIB=lib, OMP_NUM_THREADS="1")
+    pins = os.path.join(ROOT, "tests", "test_oracle3_pins.py")
+    r = subprocess.run([sys.executable, "-m", "pytest", pins + "::" + FIRST_PIN[name], "-x", "-q",
+                        "-p", "no:cacheprovider", "-p", "no:randomly"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode == 1:
+        return name, 1, (r.stdout.strip().splitlines() or [""])[-1]
+    # the named pin missed it: the fast pins, then the convergence runs
     for sel in ("not convergence", "convergence"):
         r = subprocess.run([sys.executable, "-m", "pytest",
                             os.path.join(ROOT, "tests", "test_oracle3_pins.py"), "-x", "-q",
@@ -86,7 +123,7 @@ def _run_mutant(tmp, name, old, new, src):
 
 def test_every_mutant_fails_a_pin(tmp_path):
     src = open(oracle_build.SRC3).read()
-    workers = max(1, min(4, (os.cpu_count() or 2) // 2))
+    workers = max(1, min(6, (os.cpu_count() or 2) - 2))
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         results = list(ex.map(lambda m: _run_mutant(str(tmp_path), *m, src), MUTANTS))
     survivors = [(n, last) for n, rc, last in results if rc == 0]

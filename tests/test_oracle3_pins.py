@@ -340,6 +340,38 @@ def test_polynomial_reproduction(tet, order, n):
                                        rtol=1e-9, atol=1e-9)
 
 
+def test_kept_small_stencils_are_averaged(tet):
+    # on a quadratic field every stencil reproduces the same polynomial, so
+    # the five indicators agree and chi = 1/5 for the large stencil and 1/4
+    # for each small one after step two; with C_T = 0.22 the large stencil
+    # is rejected and all four small ones kept, and their equal-weight mean
+    # is again the exact polynomial at every face point
+    m = inputs3.jittered_periodic_cube(7, 16)
+    om = tet.OracleTetMesh(m.xyz, m.tet)
+    om.setup(tet.params(order=4, ct=0.22), all_cells=False)
+    _, _, tt = om.geometry()
+    V = inputs3.unwrapped_vertices(inputs3.TetMesh(m.n, m.xyz, tt))
+    exps = [(a, b, d - a - b) for d in range(3) for a in range(d, -1, -1) for b in range(d - a, -1, -1)]
+    coefs = np.random.default_rng(21).normal(size=len(exps))
+    bary, _ = tet.face_rule(4)
+    FV = [(1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1)]
+    for i in range(0, om.n_cell, 307):
+        U = np.zeros((om.n_cell, 5))
+        U[:, 0] = 3.0
+        members = {i}
+        for k in range(5):
+            members.update(om.stencil(i, k).tolist())
+        for j in members:
+            shift = -np.round(V[j].mean(0) - V[i].mean(0))
+            U[j, 0] = 3.0 + _poly_avg(coefs, exps, V[j] + shift - V[i, 0])
+        fp, flags, _, _ = om.reconstruct_cells(U, [i])
+        assert int(flags[0]) & 0x1F == 0x0F           # density: large rejected, four small kept
+        for e in range(4):
+            P = bary @ V[i, list(FV[e])] - V[i, 0]
+            np.testing.assert_allclose(fp[0, e, :, 0], 3.0 + _poly(coefs, exps, P),
+                                       rtol=1e-9, atol=1e-9)
+
+
 def test_small_stencils_reproduce_quadratics(tet):
     m = inputs3.jittered_periodic_cube(7, 16)
     om = tet.OracleTetMesh(m.xyz, m.tet)
@@ -521,6 +553,28 @@ def test_convergence_order_wave(tet, order, ns):
         l2.append(math.sqrt((vol * e * e).sum()))
     slope = math.log(l2[0] / l2[1]) / math.log(ns[1] / ns[0])
     assert slope > order - 0.7, (l2, slope)
+
+
+def test_rk3_is_third_order_in_time(tet):
+    # on one mesh, with the linear scheme (a fixed stencil, so that no
+    # selection flips between runs), the spatial error is common to every
+    # run and the distance to a run with many small steps measures the time
+    # integrator alone: the SSP-RK3 of Shu and Osher cuts it by 2^3 per
+    # halving of the step
+    m, om = mesh_and_oracle(tet, 5, 22, 3, variant=1)
+    U0 = inputs3.smooth_wave3(m)
+    T = 2.0 * om.dt(U0, 0.4)
+
+    def run(steps):
+        U = U0.copy()
+        for _ in range(steps):
+            U = om.rk_step(U, T / steps)["U"]
+        return U
+
+    ref = run(32)
+    err = [np.abs(run(k) - ref).max() for k in (2, 4, 8)]
+    rates = [math.log2(err[i] / err[i + 1]) for i in range(2)]
+    assert min(rates) > 2.6, (err, rates)
 
 
 def test_nonphysical_detection_and_fallback(tet):

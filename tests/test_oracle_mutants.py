@@ -95,6 +95,52 @@ MUTANTS = [
      " boundary_state(*m, m->bidx[f], a0, m->fn[2 * f], m->fn[2 * f + 1], b); }\n"),
 ]
 
+# the pin expected to catch each mutant: it runs first, and the whole pin
+# suite only if it passes
+FIRST_PIN = {
+    "gauss_weight": "test_gauss_legendre_matches_numpy",
+    "basis_mean": "test_polynomial_reproduction",
+    "qr_reflector": "test_lsq_matches_numpy_lstsq",
+    "lsq_mean_volume": "test_polynomial_reproduction",
+    "lsq_rhs_volume": "test_polynomial_reproduction",
+    "beta_multiplicity": "test_smoothness_closed_forms",
+    "gamma_power": "test_selection_threshold_and_near_tie",
+    "cutoff_equality": "test_selection_exact_equality_counts_as_smooth",
+    "step_two_normalisation": "test_selection_step_two_renormalises_small_stencils",
+    "near_tie_absolute": "test_selection_threshold_and_near_tie",
+    "small_weights": "test_vjp_dot_product",
+    "face_point_direction": "test_polynomial_reproduction",
+    "hll_dissipation_sign": "test_hll_resolves_isolated_shock",
+    "roe_weight": "test_hll_resolves_isolated_shock",
+    "left_wave_speed": "test_hll_antisymmetry_and_rotation",
+    "rotate_back": "test_hll_consistency",
+    "face_point_pairing": "test_residual_cells_match_full",
+    "face_side_sign": "test_free_stream_and_conservation",
+    "residual_sign": "test_residual_cells_match_full",
+    "dt_face_length": "test_dt_closed_form_regular_mesh",
+    "rk_stage_two": "test_vjp_rk_step_against_differences",
+    "vjp_face_adjoint": "test_vjp_dot_product",
+    "vjp_target_sign": "test_vjp_dot_product",
+    "cweno_small_linear_weight": "test_cweno_weights_special_cases",
+    "cweno_optimal_subtraction": "test_cweno_reproduces_quadratics",
+    "cweno_large_scaling": "test_cweno_reproduces_quadratics",
+    "char_acoustic_energy": "test_char_basis_diagonalises_the_flux_jacobian",
+    "char_shear_energy": "test_char_basis_diagonalises_the_flux_jacobian",
+    "char_inverse_elimination": "test_char_basis_diagonalises_the_flux_jacobian",
+    "char_face_normal": "test_char_reconstruction_is_componentwise_on_the_projected_field",
+    "char_projection_state": "test_char_nonphysical_mean_keeps_conservative_variables",
+    "char_projection_transposed": "test_char_reconstruction_is_componentwise_on_the_projected_field",
+    "char_back_transform": "test_char_reconstruction_is_componentwise_on_the_projected_field",
+    "char_flags_edge": "test_char_reconstruction_is_componentwise_on_the_projected_field",
+    "wall_normal_reversal": "test_closed_box_conserves_mass_and_energy",
+    "wall_tangent_sign": "test_boundary_face_flux_on_uniform_interior",
+    "prescribed_state_ignored": "test_boundary_face_flux_on_uniform_interior",
+    "boundary_kind_swap": "test_box_free_stream",
+    "stencil_fill_order": "test_box_stencils_follow_the_rule",
+    "vjp_boundary_sign": "test_box_vjp_dot_product_and_differences",
+    "vjp_boundary_outer_fixed": "test_box_vjp_dot_product_and_differences",
+}
+
 
 def _run_mutant(tmp, name, old, new, src):
     assert src.count(old) == 1, f"mutation site of {name} not found exactly once"
@@ -108,8 +154,14 @@ def _run_mutant(tmp, name, old, new, src):
     cmd[cmd.index("-o") + 1] = lib
     cmd[-1] = cpp
     subprocess.run(cmd, check=True, capture_output=True)
-    env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="2")
-    # the fast pins first; the convergence runs only for mutants they miss
+    env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    pins = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+    r = subprocess.run([sys.executable, "-m", "pytest", pins + "::" + FIRST_PIN[name], "-x", "-q",
+                        "-p", "no:cacheprovider", "-p", "no:randomly"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode == 1:
+        return name, 1, (r.stdout.strip().splitlines() or [""])[-1]
+    # the named pin missed it: the fast pins, then the convergence runs
     for sel in ("not convergence", "convergence"):
         r = subprocess.run([sys.executable, "-m", "pytest",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-x", "-q",
@@ -123,7 +175,7 @@ def _run_mutant(tmp, name, old, new, src):
 
 def test_every_mutant_fails_a_pin(tmp_path):
     src = open(oracle_build.SRC).read()
-    workers = max(1, min(4, (os.cpu_count() or 2) // 2))
+    workers = max(1, min(6, (os.cpu_count() or 2) - 2))
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         results = list(ex.map(lambda m: _run_mutant(str(tmp_path), *m, src), MUTANTS))
     survivors = [(n, last) for n, rc, last in results if rc == 0]

@@ -260,6 +260,31 @@ def test_hll_antisymmetry_and_rotation(oracle_mod):
         np.testing.assert_allclose(fr, rot(f), rtol=1e-12, atol=1e-13)
 
 
+def test_hll_resolves_isolated_shock(oracle_mod):
+    # one shock satisfying Rankine-Hugoniot (textbook normal-shock relations,
+    # upstream Mach M on the left, shock moving with speed V along n): the
+    # Roe linearisation has the shock speed as an eigenvalue with the jump
+    # as its eigenvector, so with Roe-averaged outer speeds the HLL flux is
+    # the exact upwind flux, F(U_R) for a shock running to -n
+    rng = np.random.default_rng(9)
+    g = 1.4
+    for M, V in [(1.5, -0.4), (3.0, -0.1), (2.2, -1.0)]:
+        th = rng.uniform(0, 2 * np.pi)
+        n = np.array([np.cos(th), np.sin(th)])
+        t = np.array([-n[1], n[0]]) * rng.uniform(-0.5, 0.5)
+        rho1, p1 = 1.0, 1.0
+        w1 = M * math.sqrt(g * p1 / rho1)
+        rho2 = rho1 * (g + 1) * M * M / ((g - 1) * M * M + 2)
+        p2 = p1 * (1 + 2 * g / (g + 1) * (M * M - 1))
+        w2 = w1 * rho1 / rho2
+        uL = _state(rho1, *((w1 + V) * n + t), p1)
+        uR = _state(rho2, *((w2 + V) * n + t), p2)
+        jump = _euler_normal_flux(uR, n) - _euler_normal_flux(uL, n)
+        np.testing.assert_allclose(jump, V * (uR - uL), rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(oracle_mod.hll(uL, uR, n), _euler_normal_flux(uR, n),
+                                   rtol=1e-12, atol=1e-12)
+
+
 def test_hll_brackets_physical_speeds(oracle_mod):
     # a stationary contact (equal pressure, zero velocity) gives zero mass flux
     # only through the numerical dissipation term; a symmetric state gives
