@@ -103,13 +103,6 @@ __device__ __forceinline__ double qform3(const double* T, const double (&x)[N]) 
 // Least squares of one stencil (Sec. 2.2 eqs. 08-10), a = M d with
 // d_s = U_member(s) - U_0, for all five variables at once.  The five lanes
 // of a cell split the row's entry pairs (lane g takes pairs g, g + 5, ...)
-// so every operator byte is loaded by one lane only; each lane gathers all
-// five variables of the row's member and accumulates acc[t][k][v] for its
-// pairs.  Lanes past the row's last pair re-read that pair (the loads stay
-// unconditional) and their sums are never read.  NB rows are in flight.
-// Least squares of one stencil (Sec. 2.2 eqs. 08-10), a = M d with
-// d_s = U_member(s) - U_0, for all five variables at once.  The five lanes
-// of a cell split the row's entry pairs (lane g takes pairs g, g + 5, ...)
 // so every operator byte is loaded by one lane only.  Lane g gathers
 // variable g of the row's member (its id read from the tile's rows staged
 // in LDS, so the gather never waits behind the operator loads) and the five
@@ -232,12 +225,12 @@ __device__ __forceinline__ bool physical3(double r, double mx, double my, double
 // Reconstruction of one tile (12 cells; lane 5c + g): the least-squares
 // streams split each row's pairs over the cell's five lanes (all variables
 // per lane), and a transpose through LDS gives lane g the coefficients of
-// variable g for the selection of Sec. 3.3 with K = 4.  The small stencils'
-// indicators come first (their coefficients are dropped), then the large
-// stencil's coefficients and indicator, the selection, and - only where a
-// variable of the wavefront rejects the large stencil - the small stencils
-// again, averaged over the kept ones.  Face values of the selected
-// polynomial are written as they are formed.
+// variable g for the selection of Sec. 3.3 with K = 4.  The large stencil's
+// coefficients come first, then the small stencils' indicators (their
+// coefficients are dropped), the selection, and - only where a variable of
+// the wavefront rejects the large stencil - the small stencils again,
+// averaged over the kept ones.  Face values of the selected polynomial are
+// written as they are formed.
 template <int P>
 __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   using O = O3<P>;
