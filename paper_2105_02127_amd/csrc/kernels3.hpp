@@ -111,6 +111,16 @@ __device__ __forceinline__ double qform3(const double* T, const double (&x)[N]) 
 // pair (the loads stay unconditional) and their sums are never read.  NB
 // rows live in fixed buffers and the loop is unrolled by NB: while one row
 // is accumulated the next NB - 1 are in flight.
+// hold the small stencils' coefficients at orders 3-4 (1) or stream them
+// again where the large stencil is rejected (0)
+#ifndef TENO3_HOLD_SMALL
+#define TENO3_HOLD_SMALL 1
+#endif
+// the cell's five member values are shared through LDS (1) or by lane
+// shuffles (0)
+#ifndef TENO3_LDS_SHARE
+#define TENO3_LDS_SHARE 1
+#endif
 template <int NR, int RS, int NB>
 struct Stream3 {
   static constexpr int NPAIR = RS / 2;
@@ -121,6 +131,8 @@ struct Stream3 {
   const int32_t* sid;              // LDS: member ids of this stencil's rows, [row][kTile3]
   const double2* __restrict__ mp;  // this cell's pairs of row 0 (stride kTile3)
   const double* __restrict__ U;
+  double* xs;                      // LDS: the wavefront's 64-double exchange slot (the
+                                   // transposes' scratch, idle while a stream runs)
   int c, g;
   double u0[kVars3];
   double xq[NB];
@@ -142,8 +154,18 @@ struct Stream3 {
   __device__ __forceinline__ void accumulate(double x, const v2d (&m)[NT], Acc& acc) const {
     const int b = kVars3 * c;
     double d[kVars3];
+#if TENO3_LDS_SHARE
+    // one LDS write and three reads (the cell's five values are adjacent)
+    // instead of five two-word lane shuffles; a wavefront's LDS operations
+    // complete in order, so the next row's write cannot overtake these reads
+    xs[threadIdx.x & 63] = x;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < kVars3; ++v) d[v] = xs[b + v] - u0[v];
+#else
 #pragma unroll
     for (int v = 0; v < kVars3; ++v) d[v] = __shfl(x, b + v) - u0[v];
+#endif
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -226,13 +248,25 @@ __device__ __forceinline__ bool physical3(double r, double mx, double my, double
 // streams split each row's pairs over the cell's five lanes (all variables
 // per lane), and a transpose through LDS gives lane g the coefficients of
 // variable g for the selection of Sec. 3.3 with K = 4.  The large stencil's
-// coefficients come first, then the small stencils' indicators (their
-// coefficients are dropped), the selection, and - only where a variable of
-// the wavefront rejects the large stencil - the small stencils again,
-// averaged over the kept ones.  Face values of the selected polynomial are
-// written as they are formed.
+// coefficients come first, then the small stencils' coefficients and
+// indicators, the selection, and where a variable rejects the large stencil
+// the mean of the kept small stencils: held in registers at orders 3-4,
+// streamed again at orders 5-6 (only the stencils some lane keeps, and only
+// in wavefronts where a variable rejects).  Face values of the selected
+// polynomial are written as they are formed.
+// waves per SIMD for the order-P kernel (1: left to the compiler).  Holding
+// the small stencils' coefficients takes the order-4 kernel to 178 VGPRs (2
+// waves); capped at 3 waves it spills 16 and measured 4% faster.
+#ifndef TENO3_WAVES_P4
+#define TENO3_WAVES_P4 3
+#endif
 template <int P>
-__global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
+struct Recon3Waves {
+  static constexpr int value = P == 4 ? TENO3_WAVES_P4 : 1;
+};
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Recon3Waves<P>::value)))
+void k_reconstruct3(Recon3Args a) {
   using O = O3<P>;
   constexpr int NU = O::NU, NPT = O::NPT, NP = 4 * NPT;
   constexpr int NPSI = NP * NU, NBL = packed3<NU>(), NBS = packed3<kSmall3Coef>();
@@ -275,7 +309,8 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   const int32_t* tid = ids[wave];
   auto small_stream = [&](int k) {
     SmallS st{tid + k * kSmall3Rows * kTile3,
-              a.M + ((size_t)tile * (O::JP / 2) + k * kSmall3Blk / 2) * kTile3 + c, a.U, c, g};
+              a.M + ((size_t)tile * (O::JP / 2) + k * kSmall3Blk / 2) * kTile3 + c, a.U, sc, c,
+              g};
 #pragma unroll
     for (int q = 0; q < kVars3; ++q) st.u0[q] = u0[q];
     return st;
@@ -285,7 +320,8 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   double co[NU];
   {
     LargeS st{tid + 4 * kSmall3Rows * kTile3,
-              a.M + ((size_t)tile * (O::JP / 2) + 4 * kSmall3Blk / 2) * kTile3 + c, a.U, c, g};
+              a.M + ((size_t)tile * (O::JP / 2) + 4 * kSmall3Blk / 2) * kTile3 + c, a.U, sc, c,
+              g};
 #pragma unroll
     for (int q = 0; q < kVars3; ++q) st.u0[q] = u0[q];
     typename LargeS::Acc acc;
@@ -296,21 +332,27 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   // stencil and never reads the small ones.  Each indicator is formed in the
   // block that uses it, so that its table reads are not hoisted apart from
   // its arithmetic.
+  // At orders 3-4 the small stencils' coefficients are held for the
+  // selection (36 values per lane); at orders 5-6 that would cost a wave per
+  // SIMD, and wavefronts that reject the large stencil stream them again.
+  constexpr bool HOLD = TENO3_HOLD_SMALL && P <= 4;
+  double held[HOLD ? 4 : 1][kSmall3Coef];
   unsigned nib = 0x10u;
   int ties = 0;
   if (a.variant == 0) {
     double gk[4], gs = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
       SmallS st = small_stream(k);
       typename SmallS::Acc acc;
       st.run(acc);
       double as[kSmall3Coef];
       transpose3<SmallS::NT, kSmall3Coef>(acc, sc, lane, c, g, as);
-      const double gam = gamma3(qform3<kSmall3Coef>(Bs, as), a.eps, a.power);
+      gk[k] = gamma3(qform3<kSmall3Coef>(Bs, as), a.eps, a.power);
+      if constexpr (HOLD) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q == k) gk[q] = gam;
+        for (int l = 0; l < kSmall3Coef; ++l) held[k][l] = as[l];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) gs += gk[k];
@@ -330,13 +372,30 @@ __global__ __launch_bounds__(256) void k_reconstruct3(Recon3Args a) {
   }
   // ---- large stencil rejected: the mean of the kept small stencils (the
   // streams run for the whole wavefront; each lane takes what it keeps) ----
-  if (__any(!(nib & 0x10u))) {
+  if (HOLD && !(nib & 0x10u)) {
+    double ab[kSmall3Coef];
+#pragma unroll
+    for (int l = 0; l < kSmall3Coef; ++l) ab[l] = 0.0;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < (HOLD ? 4 : 0); ++k)
+      if ((nib >> k) & 1u) {
+#pragma unroll
+        for (int l = 0; l < kSmall3Coef; ++l) ab[l] += held[k][l];
+        ++cnt;
+      }
+#pragma unroll
+    for (int l = 0; l < NU; ++l) co[l] = (l < kSmall3Coef && cnt > 0) ? ab[l] / (double)cnt : 0.0;
+  }
+  if (!HOLD && __any(!(nib & 0x10u))) {
     double ab[kSmall3Coef];
 #pragma unroll
     for (int l = 0; l < kSmall3Coef; ++l) ab[l] = 0.0;
     int cnt = 0;
 #pragma unroll 1
     for (int k = 0; k < 4; ++k) {
+      // only the stencils some lane of the wavefront keeps
+      if (!__any(!(nib & 0x10u) && ((nib >> k) & 1u))) continue;
       SmallS st = small_stream(k);
       typename SmallS::Acc acc;
       st.run(acc);
