@@ -216,21 +216,22 @@ int launch_reconstruct(teno_solver* s, const double* U, uint16_t* flags, bool fr
   set_tie_window(a);
   a.cw_dK = 1.0 - 1.0 / s->prm.dk_prime;
   a.cw_ds = (1.0 - a.cw_dK) / 3.0;
-  const int blocks = (s->n_tiles + 3) / 4;
-  const size_t lds = (size_t)4 * a.lds_stride * sizeof(int4);
+  const int blocks = (s->n_tiles + kReconBlockWaves - 1) / kReconBlockWaves;
+  const dim3 threads(64 * kReconBlockWaves);
+  const size_t lds = (size_t)kReconBlockWaves * a.lds_stride * sizeof(int4);
   const bool cw = s->prm.variant == 2, ch = s->prm.characteristic != 0;
   int rc = TENO_OK;
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     constexpr int p = decltype(P)::value, nq = decltype(NQ)::value;
     rc = timed(s, 0, st, [&]() {
       if (ch && cw)
-        hipLaunchKernelGGL((k_reconstruct_char<p, nq, true>), dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_reconstruct_char<p, nq, true>), dim3(blocks), threads, lds, st, a);
       else if (ch)
-        hipLaunchKernelGGL((k_reconstruct_char<p, nq, false>), dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_reconstruct_char<p, nq, false>), dim3(blocks), threads, lds, st, a);
       else if (cw)
-        hipLaunchKernelGGL((k_reconstruct<p, nq, true>), dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_reconstruct<p, nq, true>), dim3(blocks), threads, lds, st, a);
       else
-        hipLaunchKernelGGL((k_reconstruct<p, nq, false>), dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_reconstruct<p, nq, false>), dim3(blocks), threads, lds, st, a);
     });
   });
   return rc;
