@@ -244,16 +244,6 @@ __device__ __forceinline__ bool physical3(double r, double mx, double my, double
   return p > 0.0;  // false for NaN
 }
 
-// Reconstruction of one tile (12 cells; lane 5c + g): the least-squares
-// streams split each row's pairs over the cell's five lanes (all variables
-// per lane), and a transpose through LDS gives lane g the coefficients of
-// variable g for the selection of Sec. 3.3 with K = 4.  The large stencil's
-// coefficients come first, then the small stencils' coefficients and
-// indicators, the selection, and where a variable rejects the large stencil
-// the mean of the kept small stencils: held in registers at orders 3-4,
-// streamed again at orders 5-6 (only the stencils some lane keeps, and only
-// in wavefronts where a variable rejects).  Face values of the selected
-// polynomial are written as they are formed.
 // waves per SIMD for the order-P kernel (1: left to the compiler).  Holding
 // the small stencils' coefficients takes the order-4 kernel to 178 VGPRs (2
 // waves); capped at 3 waves it spills 16 and measured 4% faster.
@@ -264,6 +254,17 @@ template <int P>
 struct Recon3Waves {
   static constexpr int value = P == 4 ? TENO3_WAVES_P4 : 1;
 };
+
+// Reconstruction of one tile (12 cells; lane 5c + g): the least-squares
+// streams split each row's pairs over the cell's five lanes (all variables
+// per lane), and a transpose through LDS gives lane g the coefficients of
+// variable g for the selection of Sec. 3.3 with K = 4.  The large stencil's
+// coefficients come first, then the small stencils' coefficients and
+// indicators, the selection, and where a variable rejects the large stencil
+// the mean of the kept small stencils: held in registers at orders 3-4,
+// streamed again at orders 5-6 (only the stencils some lane keeps, and only
+// in wavefronts where a variable rejects).  Face values of the selected
+// polynomial are written as they are formed.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Recon3Waves<P>::value)))
 void k_reconstruct3(Recon3Args a) {
