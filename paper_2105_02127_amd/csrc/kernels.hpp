@@ -2006,14 +2006,15 @@ __global__ __launch_bounds__(256) void k_batch_reconstruct(const BatchMeshDev* _
 // the item loop and holds them, spilling scalar registers into vector ones
 // (141 VGPRs at order 5 against 104 for one mesh); without the loop it keeps
 // the single-mesh kernel's budget.
+// Blocks of kReconBlockWaves wavefronts, as for one mesh.
 template <int PQ>
-__global__ __launch_bounds__(256) void k_batch_reconstruct_one(const BatchMeshDev* __restrict__ meshes,
-                                                               const int2* __restrict__ items,
-                                                               int n_items, int stage_k,
-                                                               int lds_stride) {
+__global__ __launch_bounds__(64 * kReconBlockWaves)
+void k_batch_reconstruct_one(const BatchMeshDev* __restrict__ meshes,
+                             const int2* __restrict__ items, int n_items, int stage_k,
+                             int lds_stride) {
   extern __shared__ int4 lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int w = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  const int w = xcd_remap(blockIdx.x, gridDim.x) * kReconBlockWaves + wave;
   if (w >= n_items) return;
   const int2 it = items[w];
   const int m = __builtin_amdgcn_readfirstlane(it.x);

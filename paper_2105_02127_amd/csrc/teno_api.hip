@@ -1143,17 +1143,20 @@ int batch_descriptors(teno_batch* b, double* const* U, const double* dt, hipStre
 
 void batch_launch_recon(teno_batch* b, int k, hipStream_t st) {
   for (const auto& L : b->rplan) {
-    const int blocks = (L.n_waves + 3) / 4;
-    const int* ws = b->start_r + L.wave0;
-    const size_t lds = (size_t)4 * L.lds_stride * sizeof(int4);
-    // one wavefront per item: the loop-free kernel over this launch's items
+    // one wavefront per item: the loop-free kernel over this launch's items,
+    // in blocks of kReconBlockWaves wavefronts; the persistent kernel in
+    // blocks of four
     const bool one = b->tune.waves_per_cu == 0;
+    const int bw = one ? kReconBlockWaves : 4;
+    const int blocks = (L.n_waves + bw - 1) / bw;
+    const int* ws = b->start_r + L.wave0;
+    const size_t lds = (size_t)bw * L.lds_stride * sizeof(int4);
     const int2* its = b->items_r + L.item0;
     switch (L.pq) {
 #define TENO_BATCH_CASE(PQ)                                                                  \
   case PQ:                                                                                   \
     if (one)                                                                                 \
-      hipLaunchKernelGGL((k_batch_reconstruct_one<PQ>), dim3(blocks), dim3(256), lds, st,    \
+      hipLaunchKernelGGL((k_batch_reconstruct_one<PQ>), dim3(blocks), dim3(64 * bw), lds, st, \
                          b->meshes, its, L.n_waves, k, L.lds_stride);                        \
     else                                                                                     \
       hipLaunchKernelGGL((k_batch_reconstruct<PQ>), dim3(blocks), dim3(256), lds, st,        \
