@@ -111,10 +111,13 @@ __device__ __forceinline__ double qform3(const double* T, const double (&x)[N]) 
 // pair (the loads stay unconditional) and their sums are never read.  NB
 // rows live in fixed buffers and the loop is unrolled by NB: while one row
 // is accumulated the next NB - 1 are in flight.
-// hold the small stencils' coefficients at orders 3-4 (1) or stream them
-// again where the large stencil is rejected (0)
+// hold small stencils' coefficients for the selection (1) or stream them
+// again where the large stencil is rejected (0); at order 6, how many
 #ifndef TENO3_HOLD_SMALL
 #define TENO3_HOLD_SMALL 1
+#endif
+#ifndef TENO3_HOLD_P6
+#define TENO3_HOLD_P6 2
 #endif
 // the cell's five member values are shared through LDS (1) or by lane
 // shuffles (0)
@@ -333,11 +336,13 @@ void k_reconstruct3(Recon3Args a) {
   // stencil and never reads the small ones.  Each indicator is formed in the
   // block that uses it, so that its table reads are not hoisted apart from
   // its arithmetic.
-  // At orders 3-4 the small stencils' coefficients are held for the
-  // selection (36 values per lane); at orders 5-6 that would cost a wave per
-  // SIMD, and wavefronts that reject the large stencil stream them again.
-  constexpr bool HOLD = TENO3_HOLD_SMALL && P <= 4;
-  double held[HOLD ? 4 : 1][kSmall3Coef];
+  // The small stencils' coefficients held for the selection: all four at
+  // orders 3-5 (36 values per lane), the first two at order 6, whose kernel
+  // already uses every register of two waves per SIMD (all four would cost a
+  // wave).  Where a variable rejects the large stencil, the wavefront streams
+  // again the stencils it does not hold and some lane keeps.
+  constexpr int NH = !TENO3_HOLD_SMALL ? 0 : (P <= 5 ? 4 : TENO3_HOLD_P6);
+  double held[NH > 0 ? NH : 1][kSmall3Coef];
   unsigned nib = 0x10u;
   int ties = 0;
   if (a.variant == 0) {
@@ -350,9 +355,9 @@ void k_reconstruct3(Recon3Args a) {
       double as[kSmall3Coef];
       transpose3<SmallS::NT, kSmall3Coef>(acc, sc, lane, c, g, as);
       gk[k] = gamma3(qform3<kSmall3Coef>(Bs, as), a.eps, a.power);
-      if constexpr (HOLD) {
+      if (k < NH) {
 #pragma unroll
-        for (int l = 0; l < kSmall3Coef; ++l) held[k][l] = as[l];
+        for (int l = 0; l < kSmall3Coef; ++l) held[k < NH ? k : 0][l] = as[l];
       }
     }
 #pragma unroll
@@ -371,45 +376,38 @@ void k_reconstruct3(Recon3Args a) {
       }
     }
   }
-  // ---- large stencil rejected: the mean of the kept small stencils (the
-  // streams run for the whole wavefront; each lane takes what it keeps) ----
-  if (HOLD && !(nib & 0x10u)) {
+  // ---- large stencil rejected: the mean of the kept small stencils, in
+  // stencil order (streams run for the whole wavefront; each lane takes
+  // what it keeps) ----
+  if (__any(!(nib & 0x10u))) {
+    const bool rej = !(nib & 0x10u);
     double ab[kSmall3Coef];
 #pragma unroll
     for (int l = 0; l < kSmall3Coef; ++l) ab[l] = 0.0;
     int cnt = 0;
 #pragma unroll
-    for (int k = 0; k < (HOLD ? 4 : 0); ++k)
-      if ((nib >> k) & 1u) {
+    for (int k = 0; k < NH; ++k)
+      if (rej && ((nib >> k) & 1u)) {
 #pragma unroll
         for (int l = 0; l < kSmall3Coef; ++l) ab[l] += held[k][l];
         ++cnt;
       }
-#pragma unroll
-    for (int l = 0; l < NU; ++l) co[l] = (l < kSmall3Coef && cnt > 0) ? ab[l] / (double)cnt : 0.0;
-  }
-  if (!HOLD && __any(!(nib & 0x10u))) {
-    double ab[kSmall3Coef];
-#pragma unroll
-    for (int l = 0; l < kSmall3Coef; ++l) ab[l] = 0.0;
-    int cnt = 0;
 #pragma unroll 1
-    for (int k = 0; k < 4; ++k) {
-      // only the stencils some lane of the wavefront keeps
-      if (!__any(!(nib & 0x10u) && ((nib >> k) & 1u))) continue;
+    for (int k = NH; k < 4; ++k) {
+      if (!__any(rej && ((nib >> k) & 1u))) continue;
       SmallS st = small_stream(k);
       typename SmallS::Acc acc;
       st.run(acc);
       double as[kSmall3Coef];
       transpose3<SmallS::NT, kSmall3Coef>(acc, sc, lane, c, g, as);
-      if (!(nib & 0x10u) && ((nib >> k) & 1u)) {
+      if (rej && ((nib >> k) & 1u)) {
 #pragma unroll
         for (int l = 0; l < kSmall3Coef; ++l) ab[l] += as[l];
         ++cnt;
       }
     }
     // the small stencils' basis is the first nine functions of the large one
-    if (!(nib & 0x10u)) {
+    if (rej) {
 #pragma unroll
       for (int l = 0; l < NU; ++l) co[l] = (l < kSmall3Coef && cnt > 0) ? ab[l] / (double)cnt : 0.0;
     }
