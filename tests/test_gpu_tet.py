@@ -268,6 +268,42 @@ def test_full_size_sampled_and_invariants(t3, tet, torch_cuda):
     assert np.abs(R0.cpu().numpy()).max() <= 1e-12 * c.flux_scale(U0)
 
 
+def test_order6_past_2e31_operator_entries_sampled(t3, tet, torch_cuda):
+    # order 6 on 38^3 x 6 = 329,232 cells: the operators hold more than 2^31
+    # doubles (18.4 GB), so every offset into them must be 64-bit on the host
+    # and on the device; sampled cells (first and last included) against the
+    # oracle, conservation over the whole mesh
+    torch = torch_cuda
+    m = inputs3.jittered_periodic_cube(38, 45)
+    U = inputs3.random_planes3(m)
+    c = Case3(t3, tet, torch, m, U, 6, "teno6_planes_N38", oracle_all=False, fallback=1)
+    info = c.lm.info()
+    stored = info.n_coef_large + (info.n_coef_large & 1)
+    per_cell = 4 * info.rows_small * (info.n_coef_small + 1) + info.rows_large * stored
+    assert per_cell * m.n_cell > 2 ** 31, per_cell * m.n_cell
+    rng = np.random.default_rng(6)
+    cells = np.sort(rng.choice(m.n_cell, 96, replace=False)).astype(np.int32)
+    cells = np.unique(np.concatenate([cells, [0, m.n_cell - 1]])).astype(np.int32)
+    fl = c.sv.empty_flags()
+    fs = c.sv.reconstruct(c.Ud, flags=fl)
+    R = c.sv.residual(c.Ud)
+    torch.cuda.synchronize()
+    fp, ofl, _, od = c.om.reconstruct_cells(U, cells)
+    g = c.flags_user(fl)[cells]
+    check_flags5(g, ofl, od["tie_mask"], what="sampled flags")
+    keep = g == ofl
+    assert_states5(c.face_states_user(fs)[cells][keep], fp.reshape(len(cells), -1, 5)[keep],
+                   rel=bar(6), what="sampled face states")
+    Ro, _ = c.om.residual_cells(U, cells)
+    scale = c.flux_scale()
+    Ra = c.user(R)
+    assert np.isfinite(Ra).all()
+    assert np.abs(Ra[cells] - Ro).max() <= bar(6) * scale
+    vol, _, _ = c.om.geometry()
+    tot = (vol[:, None] * Ra).sum(0)
+    assert np.abs(tot).max() <= 1e-12 * scale * vol.sum()
+
+
 def test_call_errors(t3, tet, torch_cuda):
     torch = torch_cuda
     m = inputs3.jittered_periodic_cube(5, 71)
