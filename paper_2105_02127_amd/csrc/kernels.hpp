@@ -1727,16 +1727,24 @@ __device__ __forceinline__ unsigned quad_bcast_u(unsigned x, int k) {
   }
 }
 
+// wavefronts per block of the adjoint reconstruction (one tile each); one,
+// as for the forward kernels, measured 4% faster on the backward pass
+#ifndef TENO_ADJ_BLOCK_WAVES
+#define TENO_ADJ_BLOCK_WAVES 1
+#endif
+constexpr int kAdjBlockWaves = TENO_ADJ_BLOCK_WAVES;
+
 template <int P, int NQ>
-__global__ __launch_bounds__(256) void k_adj_recon(AdjReconArgs a) {
+__global__ __launch_bounds__(64 * kAdjBlockWaves) void k_adj_recon(AdjReconArgs a) {
   using O = OrderT<P>;
   constexpr int NU = O::NU;
   constexpr int NP = 3 * NQ;
   constexpr bool SL = lane_rows(kSmallCoef, true), LL = large_lane_rows(NU, true);
   static_assert(kTile == 16, "four lanes per cell");
-  extern __shared__ double lds_acc[];  // 4 wavefronts x ustride x 4
+  extern __shared__ double lds_acc[];  // kAdjBlockWaves wavefronts x ustride x 4
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tile = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
+  const int tile =
+      __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * kAdjBlockWaves + wave);
   if (tile >= a.n_tiles) return;  // whole wavefront leaves together
   double* acc = lds_acc + (size_t)wave * a.ustride * 4;
   for (int i = lane; i < 4 * a.ustride; i += 64) acc[i] = 0.0;

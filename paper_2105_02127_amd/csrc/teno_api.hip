@@ -336,7 +336,7 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
   ra.n_cell = s->n_cell;
   ra.n_tiles = s->n_tiles;
   ra.n_pad = s->n_pad;
-  const int tblocks = (s->n_tiles + 3) / 4;
+  const int tblocks = (s->n_tiles + kAdjBlockWaves - 1) / kAdjBlockWaves;
   const int qblocks = (int)(((int64_t)s->n_cell * 4 + 255) / 256);
   dispatch(s->d.order, s->d.nq, [&](auto P, auto NQ) {
     rc = timed(s, 3, st, [&]() {
@@ -345,7 +345,8 @@ int launch_vjp(teno_solver* s, const double* U, const uint16_t* flags, const dou
         hipLaunchKernelGGL((k_adj_boundary<decltype(NQ)::value>), dim3((s->n_bface + 255) / 256),
                            dim3(256), 0, st, ff, (const int*)s->bface, s->n_bface);
       hipLaunchKernelGGL((k_adj_recon<decltype(P)::value, decltype(NQ)::value>), dim3(tblocks),
-                         dim3(256), (size_t)4 * s->ustride * 4 * sizeof(double), st, ra);
+                         dim3(64 * kAdjBlockWaves),
+                         (size_t)kAdjBlockWaves * s->ustride * 4 * sizeof(double), st, ra);
       hipLaunchKernelGGL(k_adj_gather, dim3(qblocks), dim3(256), 0, st, s->own, s->tbar,
                          s->rev_ptr, s->rev_ent, s->n_cell, extra, beta, out);
     });
