@@ -1308,14 +1308,16 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
 }
 
 // Per-order occupancy targets (waves per SIMD; 1 leaves the budget to the
-// compiler): order 3 in rows-by-lane blocks needs 132 registers left alone
-// and runs faster held to 128 (four waves); the other orders measured best
-// unconstrained.
+// compiler): TENO at order 3 in rows-by-lane blocks needs 132 registers left
+// alone and runs faster held to 128 (four waves); TENO at order 5 (130
+// registers, 2 spilled when held to 128) measured 1% faster at four waves
+// with one wavefront per block.  The other kernels measured best
+// unconstrained (order 4 and CWENO 6 lose 10-14% at four waves).
 template <int P, bool CW>
 struct ReconWaves {
   static constexpr int value = TENO_RECON_WAVES_PER_EU > 0 ? TENO_RECON_WAVES_PER_EU
-                               : (P == 3 && !CW && lane_rows(kSmallCoef, true)) ? 4
-                                                                           : 1;
+                               : ((P == 3 || P == 5) && !CW && lane_rows(kSmallCoef, true)) ? 4
+                                                                                        : 1;
 };
 
 // Wavefronts per block of the reconstruction kernels (one tile each).  One
