@@ -400,11 +400,12 @@ def test_vjp_rk_step_matches_oracle(teno, oracle_mod, torch_cuda):
 # --------------------------------------------------------------------------
 # full-size workloads: sampled cells the oracle computes one by one
 # --------------------------------------------------------------------------
-def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0, n=None):
+def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0, n=None, variant=0):
     w, m, U = inputs.make_workload(key, n=n)
-    print(f"[full-size] {w['name']} n={w['n']} cells={m.n_cell} characteristic={characteristic}",
-          flush=True)
-    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1, characteristic=characteristic)
+    print(f"[full-size] {w['name']} n={w['n']} cells={m.n_cell} characteristic={characteristic} "
+          f"variant={variant}", flush=True)
+    lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1, characteristic=characteristic,
+                                      variant=variant)
     info = lm.info()
     if n is not None and n > 1024:
         # past 2^31 operator entries: every offset into M must be 64-bit
@@ -412,8 +413,8 @@ def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0, n=Non
     sv = teno.Solver(lm)
     perm = lm.perm
     om = oracle_mod.OracleMesh(m.xy, m.tri)
-    om.setup(oracle_mod.params(order=w["order"], fallback=1, characteristic=characteristic),
-             all_cells=False)
+    om.setup(oracle_mod.params(order=w["order"], fallback=1, characteristic=characteristic,
+                               variant=variant), all_cells=False)
     rng = np.random.default_rng(key)
     cells = np.unique(np.concatenate([rng.integers(0, m.n_cell, n_sample),
                                       perm[-5:], perm[:3]]))       # include the ragged tail
@@ -534,6 +535,16 @@ def test_full_size_teno5_khi_sampled(teno, oracle_mod, torch_cuda):
 def test_full_size_teno5_khi_characteristic_sampled(teno, oracle_mod, torch_cuda):
     # characteristic variables on the KHI workload at full size
     _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=64, characteristic=1)
+
+
+def test_full_size_cweno5_khi_sampled(teno, oracle_mod, torch_cuda):
+    # CWENO5 on the KHI workload at full size, as the bench times it
+    _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=64, variant=2)
+
+
+def test_full_size_cweno5_khi_characteristic_sampled(teno, oracle_mod, torch_cuda):
+    # CWENO5 in characteristic variables on the KHI workload at full size
+    _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=64, characteristic=1, variant=2)
 
 
 def test_rk_step_dt_equals_step_then_max_dt(teno, oracle_mod, torch_cuda):
