@@ -269,6 +269,35 @@ def test_full_size_sampled_and_invariants(t3, tet, torch_cuda):
     assert np.abs(R0.cpu().numpy()).max() <= 1e-12 * c.flux_scale(U0)
 
 
+def test_full_size_explosion_sampled(t3, tet, torch_cuda):
+    # the 3D explosion workload of the benchmark at its size (60^3 x 6 =
+    # 1,296,000 cells in the box [-1, 1]^3, open sides, TENO4): face states,
+    # flags and residuals at sampled cells, boundary cells included
+    torch = torch_cuda
+    w, m, U = inputs3.make_workload3("explosion3_N60")
+    c = Case3(t3, tet, torch, m, U, w["order"], "explosion3_N60", period=m.period,
+              oracle_all=False, fallback=w["fallback"])
+    bcells = np.unique(c.lm.boundary_faces()[1])
+    rng = np.random.default_rng(7)
+    cells = np.concatenate([rng.choice(m.n_cell, 96, replace=False), rng.choice(bcells, 32, replace=False),
+                            [0, m.n_cell - 1], c.perm[-3:]])
+    cells = np.unique(cells).astype(np.int32)
+    fl = c.sv.empty_flags()
+    fs = c.sv.reconstruct(c.Ud, flags=fl)
+    R = c.sv.residual(c.Ud)
+    torch.cuda.synchronize()
+    fp, ofl, _, od = c.om.reconstruct_cells(U, cells)
+    g = c.flags_user(fl)[cells]
+    check_flags5(g, ofl, od["tie_mask"], what="sampled flags")
+    keep = g == ofl
+    assert_states5(c.face_states_user(fs)[cells][keep], fp.reshape(len(cells), -1, 5)[keep],
+                   what="sampled face states")
+    Ro, _ = c.om.residual_cells(U, cells)
+    Ra = c.user(R)
+    assert np.isfinite(Ra).all()
+    assert np.abs(Ra[cells] - Ro).max() <= REL * c.flux_scale()
+
+
 def test_order6_past_2e31_operator_entries_sampled(t3, tet, torch_cuda):
     # order 6 on 38^3 x 6 = 329,232 cells: the operators hold more than 2^31
     # doubles (18.4 GB), so every offset into them must be 64-bit on the host
