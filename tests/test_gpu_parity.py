@@ -400,8 +400,11 @@ def test_vjp_rk_step_matches_oracle(teno, oracle_mod, torch_cuda):
 # --------------------------------------------------------------------------
 # full-size workloads: sampled cells the oracle computes one by one
 # --------------------------------------------------------------------------
-def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0, n=None, variant=0):
+def _sampled(teno, oracle_mod, torch, key, n_sample=160, characteristic=0, n=None, variant=0,
+             order=None):
     w, m, U = inputs.make_workload(key, n=n)
+    if order is not None:
+        w = dict(w, order=order)
     print(f"[full-size] {w['name']} n={w['n']} cells={m.n_cell} characteristic={characteristic} "
           f"variant={variant}", flush=True)
     lm = teno.Mesh(m.xy, m.tri).setup(order=w["order"], fallback=1, characteristic=characteristic,
@@ -535,6 +538,16 @@ def test_full_size_teno5_khi_sampled(teno, oracle_mod, torch_cuda):
 def test_full_size_teno5_khi_characteristic_sampled(teno, oracle_mod, torch_cuda):
     # characteristic variables on the KHI workload at full size
     _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=64, characteristic=1)
+
+
+@pytest.mark.parametrize("order,variant,characteristic", [(3, 0, 0), (4, 0, 0), (6, 0, 0), (6, 2, 0),
+                                                        (6, 0, 1)])
+def test_full_size_khi_other_schemes_sampled(teno, oracle_mod, torch_cuda, order, variant,
+                                             characteristic):
+    # the rest of the KHI timing legs at full size: TENO3, TENO4, TENO6,
+    # CWENO6 and characteristic TENO6
+    _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=48, characteristic=characteristic,
+             variant=variant, order=order)
 
 
 def test_full_size_cweno5_khi_sampled(teno, oracle_mod, torch_cuda):
