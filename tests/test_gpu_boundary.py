@@ -216,21 +216,23 @@ def test_box_vjp_matches_oracle(teno, oracle_mod, torch_cuda, order, kinds):
                    what=f"box lam_in p={order}")
 
 
-def test_full_size_double_mach_sampled(teno, oracle_mod, torch_cuda):
-    # the paper's DMR workload at its timing size (369,800 cells), TENO5, in
-    # the bench's launch configuration; sampled cells against the oracle
+@pytest.mark.parametrize("order,variant", [(5, 0), (3, 0), (4, 0), (6, 0), (5, 2), (6, 2)])
+def test_full_size_double_mach_sampled(teno, oracle_mod, torch_cuda, order, variant):
+    # the paper's DMR workload at its timing size (369,800 cells), every
+    # scheme the bench times on it, in the bench's launch configuration;
+    # sampled cells against the oracle
     torch = torch_cuda
     w, m, U = inputs.make_workload(7)
-    print(f"[full-size] {w['name']} cells={m.n_cell}", flush=True)
+    print(f"[full-size] {w['name']} cells={m.n_cell} order={order} variant={variant}", flush=True)
     lm = teno.Mesh(m.xy, m.tri, period=m.period)
     verts, _ = lm.boundary_faces()
     kind, state = inputs.double_mach_boundary(m, verts, 0.0)
     lm.set_boundary(kind, state)
-    lm.setup(order=w["order"], fallback=1)
+    lm.setup(order=order, fallback=1, variant=variant)
     sv = teno.Solver(lm)
     om = oracle_mod.OracleMesh(m.xy, m.tri, period=m.period)
     om.set_boundary(kind, state)
-    om.setup(oracle_mod.params(order=w["order"], fallback=1), all_cells=False)
+    om.setup(oracle_mod.params(order=order, fallback=1, variant=variant), all_cells=False)
     perm = lm.perm
     inv = np.empty_like(perm)
     inv[perm] = np.arange(m.n_cell)
