@@ -230,3 +230,54 @@ def test_degenerate_meshes_are_refused(teno, oracle_mod):
         teno.Mesh(box.xy, box.tri, period=box.period).setup(order=6)
     with pytest.raises(RuntimeError, match="too few"):
         oracle_mod.OracleMesh(box.xy, box.tri, period=box.period).setup(oracle_mod.params(order=6))
+
+
+LDL_CHECK = r"""
+#include <cmath>
+#include <cstdio>
+#include "tables.h"
+using namespace teno;
+// max |L D L^T - B| / max |B| of the compile-time factor, and the smallest
+// pivot relative to the largest, for the smoothness form of degree R
+template <int R>
+void check() {
+  using S = SmoothForm<R>;
+  double worst = 0.0, scale = 0.0, dmin = 1e300, dmax = 0.0;
+  for (int i = 0; i < S::N; ++i)
+    for (int j = 0; j < S::N; ++j) {
+      double s = 0.0;
+      for (int k = 0; k <= (i < j ? i : j); ++k) s += S::LDL.Lt[k][i] * S::LDL.d[k] * S::LDL.Lt[k][j];
+      worst = std::fmax(worst, std::fabs(s - S::B.v[i][j]));
+      scale = std::fmax(scale, std::fabs(S::B.v[i][j]));
+    }
+  for (int k = 0; k < S::N; ++k) {
+    dmin = std::fmin(dmin, S::LDL.d[k]);
+    dmax = std::fmax(dmax, S::LDL.d[k]);
+    if (S::LDL.Lt[k][k] != 1.0) worst = 1.0;
+  }
+  std::printf("%d %.3e %.3e\n", R, worst / scale, dmin / dmax);
+}
+int main() {
+  check<2>();
+  check<3>();
+  check<4>();
+  check<5>();
+}
+"""
+
+
+def test_smoothness_form_factor(tmp_path):
+    # the characteristic kernel forms its Gram matrices through B = L D L^T
+    # (unit L, D > 0): the compile-time factor must reproduce B to round-off
+    # and have positive pivots (B is positive definite on the zero-mean basis)
+    src = tmp_path / "ldl.cpp"
+    src.write_text(LDL_CHECK)
+    exe = tmp_path / "ldl"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", os.path.join(ROOT, "paper_2105_02127_amd", "csrc"),
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    rows = [line.split() for line in out if line.strip()]
+    assert [int(r[0]) for r in rows] == [2, 3, 4, 5]
+    for r, rel, piv in rows:
+        assert float(rel) < 1e-14, (r, rel)
+        assert float(piv) > 0.0, (r, piv)
