@@ -1144,6 +1144,97 @@ __device__ __forceinline__ void char_edges_gram(const ReconArgs& a, const double
   if (live && writer && ties) atomicAdd(&a.diag->near_ties, (unsigned long long)ties);
 }
 
+// Characteristic CWENO (Sec. 2.4 in the variables of Sec. 2.3) with the
+// indicators of char_edges_gram: the weights of variable v on an edge come
+// from L_v^T G_k L_v.  The CWENO polynomial is a linear combination of the
+// stencils' polynomials, P = lK P_K + sum_k l_k p_k with lK = (w_K/d_K)/S and
+// l_k = (alpha_k - d_k w_K/d_K)/S, so each stencil is evaluated at the edge's
+// Gauss points in conservative variables and only those point values are
+// projected (four stencils x NQ points instead of every coefficient).
+template <int P, int NQ>
+__device__ __forceinline__ void char_edges_cweno_gram(const ReconArgs& a,
+                                                      const double (&as)[3][5],
+                                                      const double (&aK)[OrderT<P>::NU],
+                                                      double u0, int cell, bool live,
+                                                      bool writer, int g, int v, int c,
+                                                      int4* stage) {
+  using O = OrderT<P>;
+  constexpr int NU = O::NU;
+  const bool avg_ok = physical(quad_bcast<0>(u0), quad_bcast<1>(u0), quad_bcast<2>(u0),
+                               quad_bcast<3>(u0), a.gamma);
+  const double* __restrict__ gc = a.geo + (size_t)(live ? cell : 0) * 10;
+  const int side = a.nbinfo[live ? cell : 0].w;  // face normals point out of the L side
+  double* gram = reinterpret_cast<double*>(stage) + c * 40;
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gram_rows<2>(as[k], v, gram + 10 * k);
+  gram_rows<O::R>(aK, v, gram + 30);
+  wave_lds_sync();
+  bool fp_ok = true;
+  const CharCore core = char_core(char_state(u0, a.gamma));
+  auto state = [&]() { return char_expand(core, a.gamma); };
+  static_for<0, 3>([&](auto E) {
+    constexpr int e = E;
+    __builtin_amdgcn_sched_barrier(0);
+    const double sg = ((side >> (6 + e)) & 1) ? 1.0 : -1.0;
+    const double nx = sg * gc[3 * e], ny = sg * gc[3 * e + 1];
+    double lrow[4];
+    char_lrow_lane(state(), nx, ny, avg_ok, v, lrow);
+    int goff = c * 40;
+    asm volatile("" : "+v"(goff));
+    const double* gm = reinterpret_cast<const double*>(stage) + goff;
+    double q[10];
+    gram_weights(lrow, q);
+    const double w0 = a.cw_ds * gamma_k(gram_dot(gm, q), a.eps, a.power);
+    const double w1 = a.cw_ds * gamma_k(gram_dot(gm + 10, q), a.eps, a.power);
+    const double w2 = a.cw_ds * gamma_k(gram_dot(gm + 20, q), a.eps, a.power);
+    const double wK = a.cw_dK * gamma_k(gram_dot(gm + 30, q), a.eps, a.power);
+    const double iS = 1.0 / (((w0 + w1) + w2) + wK);
+    const double cK = wK / a.cw_dK;
+    const double lK = cK * iS;
+    const double l0 = (w0 - cK * a.cw_ds) * iS, l1 = (w1 - cK * a.cw_ds) * iS,
+                 l2 = (w2 - cK * a.cw_ds) * iS;
+    double rrow[4];
+    char_rrow(state(), nx, ny, avg_ok, v, rrow);
+    const double* __restrict__ fb = &FaceBasis<O::R, NQ>::P.v[e * NQ][0];
+#pragma unroll
+    for (int kq = 0; kq < NQ; ++kq) {
+      // the four stencils' values of the lane's conservative variable
+      double pK = 0.0, p0 = 0.0, p1 = 0.0, p2 = 0.0;
+#pragma unroll
+      for (int l = 0; l < NU; ++l) pK = fma(aK[l], fb[kq * NU + l], pK);
+#pragma unroll
+      for (int l = 0; l < 5; ++l) {
+        p0 = fma(as[0][l], fb[kq * NU + l], p0);
+        p1 = fma(as[1][l], fb[kq * NU + l], p1);
+        p2 = fma(as[2][l], fb[kq * NU + l], p2);
+      }
+      const double dw = lK * quad_dot(lrow, pK) +
+                        ((l0 * quad_dot(lrow, p0) + l1 * quad_dot(lrow, p1)) +
+                         l2 * quad_dot(lrow, p2));
+      const double val = u0 + quad_dot(rrow, dw);
+      fp_ok = fp_ok && physical(quad_bcast<0>(val), quad_bcast<1>(val), quad_bcast<2>(val),
+                                quad_bcast<3>(val), a.gamma);
+      if (live && writer) a.fp[((size_t)(e * NQ + kq) * a.n_pad + cell) * 4 + v] = val;
+    }
+    if (a.flags && live && g == 0) a.flags[(size_t)e * a.n_cell + cell] = 0;
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- non-physical states (all four lanes of a cell agree) ----
+  if (live && g == 0 && !(avg_ok && fp_ok)) {
+    atomicAdd(&a.diag->nonphysical, 1ull);
+    atomicMin(&a.diag->first_bad, (long long)a.user_of[cell]);
+  }
+  if (!fp_ok && avg_ok && a.fallback) {
+    if (live && writer)
+      for (int q = 0; q < 3 * NQ; ++q) a.fp[((size_t)q * a.n_pad + cell) * 4 + v] = u0;
+    if (live && g == 0) atomicAdd(&a.diag->fallbacks, 1ull);
+  }
+}
+
+#ifndef TENO_CHAR_CWENO_GRAM
+#define TENO_CHAR_CWENO_GRAM 1
+#endif
 template <int P, int NQ, bool CW = false, bool CH = false>
 __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, int lane,
                                                  int4* stage) {
@@ -1254,6 +1345,8 @@ __device__ __forceinline__ void reconstruct_tile(const ReconArgs& a, int tile, i
 #if TENO_CHAR_GRAM
     if constexpr (!CW)
       char_edges_gram<P, NQ>(a, as, aK, u0, cell, live, writer, g, v, c, stage);
+    else if constexpr (TENO_CHAR_CWENO_GRAM)
+      char_edges_cweno_gram<P, NQ>(a, as, aK, u0, cell, live, writer, g, v, c, stage);
     else
 #endif
       char_edges<P, NQ, CW>(a, as, aK, u0, cell, live, writer, g, v);

@@ -148,7 +148,9 @@ def test_cweno_matches_oracle(teno, oracle_mod, torch_cuda, order, ic):
 
 @pytest.mark.parametrize("order,variant,ic", [(3, 0, "random_lines"), (4, 0, "random_lines"),
                                                (5, 0, "random_lines"), (6, 0, "wave_plus_jump"),
-                                               (5, 2, "random_lines"), (4, 1, "random_lines")])
+                                               (5, 2, "random_lines"), (4, 1, "random_lines"),
+                                               (3, 2, "random_lines"), (4, 2, "random_lines"),
+                                               (6, 2, "wave_plus_jump")])
 def test_characteristic_matches_oracle(teno, oracle_mod, torch_cuda, order, variant, ic):
     # selection in characteristic variables, edge by edge (Sec. 2.3): face
     # states, per-edge flags, residual and an RK step with its flags
