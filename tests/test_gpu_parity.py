@@ -543,11 +543,11 @@ def test_full_size_teno5_khi_characteristic_sampled(teno, oracle_mod, torch_cuda
 
 
 @pytest.mark.parametrize("order,variant,characteristic", [(3, 0, 0), (4, 0, 0), (6, 0, 0), (6, 2, 0),
-                                                        (6, 0, 1)])
+                                                        (6, 0, 1), (6, 2, 1)])
 def test_full_size_khi_other_schemes_sampled(teno, oracle_mod, torch_cuda, order, variant,
                                              characteristic):
     # the rest of the KHI timing legs at full size: TENO3, TENO4, TENO6,
-    # CWENO6 and characteristic TENO6
+    # CWENO6 and characteristic TENO6; and characteristic CWENO6
     _sampled(teno, oracle_mod, torch_cuda, 6, n_sample=48, characteristic=characteristic,
              variant=variant, order=order)
 
