@@ -119,7 +119,8 @@ class Box:
 
 
 @pytest.mark.parametrize("order,variant,characteristic", [(3, 0, 0), (4, 0, 0), (5, 0, 0),
-                                                          (6, 0, 0), (5, 2, 0), (5, 0, 1)])
+                                                          (6, 0, 0), (5, 2, 0), (5, 0, 1),
+                                                          (5, 2, 1)])
 def test_box_matches_oracle(teno, oracle_mod, torch_cuda, order, variant, characteristic):
     torch = torch_cuda
     b = Box(teno, oracle_mod, torch, 30, 16, 40 + order, order, variant, characteristic)
@@ -289,7 +290,8 @@ def test_tubes_match_oracle(teno, oracle_mod, torch_cuda, ic, order):
 
 
 @pytest.mark.parametrize("key,order,variant,characteristic", [
-    (8, 3, 0, 0), (8, 5, 0, 0), (9, 4, 0, 0), (9, 6, 0, 0), (8, 5, 2, 0), (9, 5, 0, 1)])
+    (8, 3, 0, 0), (8, 5, 0, 0), (9, 4, 0, 0), (9, 6, 0, 0), (8, 5, 2, 0), (9, 5, 0, 1),
+    (8, 5, 2, 1)])
 def test_explosions_match_oracle(teno, oracle_mod, torch_cuda, key, order, variant, characteristic):
     # the paper's explosion problems (Sec. 5.6) on the disc at h = 1/50
     # (18,218 cells), transmissive rim: three RK steps against the oracle
